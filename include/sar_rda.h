@@ -1,0 +1,208 @@
+/*
+ * sar_rda.h -- C ABI of the MI355X (gfx950) SAR Range Doppler Algorithm
+ * library, libsar_rda.so.
+ *
+ * The method is the kernel-fused Range Doppler Algorithm of "From 8 Seconds
+ * to 370 ms: Kernel-Fused SAR Imaging on Apple Silicon via Single-Dispatch
+ * FFT Pipelines" (arXiv 2604.03585):
+ *   Sec. II.B  one line = FFT -> matched-filter multiply -> IFFT, fused so
+ *              the line is read once from and written once to device memory;
+ *   Sec. II.C  the inverse transform is the conjugated forward transform
+ *              scaled by 1/N;
+ *   Sec. IV.A  range compression of every range line, azimuth FFT, range
+ *              cell migration correction (RCMC) by sinc interpolation in the
+ *              range-Doppler domain, azimuth compression (filter multiply +
+ *              IFFT); Sec. IV.B the corner turn between the two passes.
+ *
+ * Conventions shared by every entry point:
+ *  - Scene data are interleaved complex64 (float re, float im), row-major.
+ *    Raw echo and range-compressed data are [Na][Nr] (one range line per
+ *    row); after the corner turn the azimuth pass works on [Nr][Na].
+ *  - Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
+ *    tensors), 16-byte aligned.  The caller owns every data and workspace
+ *    buffer; a plan owns only its own tables.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every execute call is asynchronous: it validates its arguments on the
+ *    host, enqueues kernels and returns.  A returned status reports argument
+ *    or launch errors only; faults during execution surface at the caller's
+ *    next synchronisation as HIP errors.
+ *  - On any non-OK status nothing has been enqueued (validation precedes the
+ *    first launch) except for SAR_ERR_HIP, which may follow earlier launches
+ *    of the same call.  sar_last_error() then returns a message (per thread).
+ *  - Plans are immutable after sar_plan(); one plan may be used from several
+ *    streams at once as long as each call has its own data and workspace.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef SAR_RDA_H
+#define SAR_RDA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sar_plan_s* sar_plan_t;
+typedef struct sar_batch_s* sar_batch_t;
+
+typedef enum {
+    SAR_OK = 0,
+    SAR_ERR_NULL = 1,        /* a required pointer is NULL                    */
+    SAR_ERR_BAD_SIZE = 2,    /* a size is not a power of two / out of range  */
+    SAR_ERR_BAD_PARAM = 3,   /* an enum or physical parameter is invalid     */
+    SAR_ERR_ALIAS = 4,       /* buffers overlap where they must not          */
+    SAR_ERR_NO_MEMORY = 5,   /* a device or host allocation failed           */
+    SAR_ERR_HIP = 6,         /* a HIP runtime call or launch failed          */
+    SAR_ERR_UNSUPPORTED = 7  /* valid request this build does not implement  */
+} sar_status;
+
+typedef enum { SAR_AZ_LFM = 0, SAR_AZ_HYPERBOLIC = 1 } sar_az_model;
+typedef enum { SAR_FP32 = 0, SAR_SPLIT_FP16 = 1, SAR_SPLIT_BF16 = 2 } sar_precision;
+typedef enum { SAR_FUSED = 0, SAR_UNFUSED = 1 } sar_schedule;
+
+/*
+ * Processing parameters (normalised units: one range cell = 1, one pulse
+ * repetition interval = 1, so chirp rates are cycles/sample^2, `v` is in
+ * cells/pulse and `lambda` in cells).
+ *
+ *  Nr, Na          range / azimuth line lengths, powers of two, 64..16384.
+ *  range_len       L_r, range replica length, 1..Nr; range_tbp its
+ *                  time-bandwidth product (K_r = tbp / L_r^2).  The range
+ *                  filter is H_r = conj(DFT(h_r)) of the circularly centred
+ *                  up-chirp replica h_r[u mod Nr] = exp(j pi K_r u^2),
+ *                  u = -L_r/2 .. L_r/2-1  (Sec. II.B; H_r itself is not
+ *                  specified by the paper, this is our reading).
+ *  az_model        SAR_AZ_LFM: zero-migration azimuth; H_a is built like H_r
+ *                  from the down-chirp exp(-j pi K_a u^2), u over az_len
+ *                  samples, K_a = az_tbp / az_len^2.
+ *                  SAR_AZ_HYPERBOLIC: exact-geometry azimuth filter
+ *                  exp(+j 4 pi R0 D(f) / lambda), D(f) = sqrt(1-(lambda f/2v)^2),
+ *                  R0 = r_near + n, after RCMC (Sec. IV.A steps 3-4).
+ *  lambda, v, r_near  hyperbolic geometry (ignored for LFM).
+ *  rcmc_taps       0 (no RCMC) or 8: Kaiser-windowed sinc, taps -3..4 about
+ *                  floor(p), weights normalised to unit sum; rcmc_beta is the
+ *                  Kaiser beta (2.5 by default).
+ *  precision       SAR_FP32, or the split-FP16 / split-BF16 MFMA butterflies.
+ *  schedule        SAR_FUSED (one kernel per line pass) or SAR_UNFUSED
+ *                  (separate FFT, multiply and IFFT dispatches, Sec. II.B
+ *                  Fig. 1 top) -- the comparator.
+ *  transpose_back  0: sar_rda_execute leaves the image as [Nr][Na];
+ *                  1: it is turned back to [Na][Nr].
+ */
+typedef struct {
+    uint32_t struct_size;     /* must equal sizeof(sar_params) */
+    int32_t  Nr, Na;
+    int32_t  range_len;
+    double   range_tbp;
+    int32_t  az_model;
+    int32_t  az_len;
+    double   az_tbp;
+    double   lambda, v, r_near;
+    int32_t  rcmc_taps;
+    double   rcmc_beta;
+    int32_t  precision, schedule, transpose_back;
+} sar_params;
+
+/* Build a plan: validates `p`, allocates the plan's device tables and fills
+ * them on `stream` with FP64 generator kernels (twiddles exp(-2 pi i k/N),
+ * the matched filters with the IFFT's 1/N folded in, and for the hyperbolic
+ * model the per-Doppler-bin RCMC stretch 1/D-1 and phase rate 2D/lambda).
+ * Synchronises `stream` before returning.  *out receives the plan. */
+sar_status sar_plan(const sar_params* p, void* stream, sar_plan_t* out);
+
+/* Free a plan.  The caller must have synchronised every stream that used it. */
+void sar_plan_destroy(sar_plan_t plan);
+
+/* Bytes of device workspace sar_rda_execute / sar_azimuth_compress need:
+ * 8 * Na * Nr (one scene-sized complex64 buffer). */
+size_t sar_workspace_bytes(sar_plan_t plan);
+
+/* Range compression (Sec. IV.A step 1): every row of in_dev [Na][Nr] goes
+ * through FFT, times H_r, IFFT into out_dev [Na][Nr].  in_dev == out_dev is
+ * allowed; partial overlap is SAR_ERR_ALIAS. */
+sar_status sar_range_compress(sar_plan_t plan, const void* in_dev, void* out_dev,
+                              void* stream);
+
+/* Corner turn (Sec. IV.B): out_dev[c][r] = in_dev[r][c] for an in_dev of
+ * rows x cols complex64 (each 1..2^20, rows*cols <= 2^31).  Bit-exact.
+ * Out of place only (overlap is SAR_ERR_ALIAS).  `plan` may be NULL. */
+sar_status sar_corner_turn(sar_plan_t plan, const void* in_dev, void* out_dev,
+                           int32_t rows, int32_t cols, void* stream);
+
+/* Azimuth compression on range-major data in_dev [Nr][Na] into out_dev
+ * [Nr][Na] (Sec. IV.A steps 2-4).  LFM: FFT * H_a * IFFT per row; in_dev ==
+ * out_dev allowed and work_dev unused (may be NULL).  Hyperbolic: azimuth
+ * FFT into work_dev, then RCMC + azimuth phase + IFFT into out_dev; in_dev
+ * may equal out_dev, work_dev (>= sar_workspace_bytes) must overlap neither. */
+sar_status sar_azimuth_compress(sar_plan_t plan, const void* in_dev, void* out_dev,
+                                void* work_dev, void* stream);
+
+/* Whole RDA (Sec. IV.A): raw_dev [Na][Nr] -> img_dev ([Nr][Na], or [Na][Nr]
+ * with transpose_back).  raw_dev is read only.  work_dev holds
+ * sar_workspace_bytes(plan).  The three buffers must be pairwise disjoint. */
+sar_status sar_rda_execute(sar_plan_t plan, const void* raw_dev, void* img_dev,
+                           void* work_dev, void* stream);
+
+/* ---- individual steps, for step-by-step testing and the unfused path ---- */
+
+/* Forward (inverse = 0) or inverse (inverse = 1, including 1/N) FFT of
+ * `lines` contiguous lines of length N = Nr (axis 0) or Na (axis 1).
+ * in_dev == out_dev allowed. */
+sar_status sar_fft_lines(sar_plan_t plan, int32_t axis, int32_t inverse,
+                         const void* in_dev, void* out_dev, int32_t lines,
+                         void* stream);
+
+/* Azimuth FFT of the range-Doppler pass (Sec. IV.A step 2): every row of
+ * in_dev [Nr][Na] -> out_dev [Nr][Na].  Same as sar_fft_lines(axis 1). */
+sar_status sar_azimuth_fft(sar_plan_t plan, const void* in_dev, void* out_dev,
+                           void* stream);
+
+/* RCMC + exact-geometry azimuth phase + azimuth IFFT (Sec. IV.A steps 3-4)
+ * on range-Doppler data A_dev [Nr][Na] -> out_dev [Nr][Na].  Hyperbolic
+ * plans only.  A_dev and out_dev must not overlap (RCMC reads rows up to
+ * ~18 cells away). */
+sar_status sar_rcmc_azimuth(sar_plan_t plan, const void* A_dev, void* out_dev,
+                            void* stream);
+
+/* Copy one of the plan's tables to host memory (tests of the FP64
+ * generators).  which: 0 H_r (Nr complex64, includes 1/Nr), 1 H_a (Na
+ * complex64, includes 1/Na; LFM only), 2 RCMC stretch 1/D-1 (Na doubles;
+ * hyperbolic), 3 phase rate 2D/lambda (Na doubles; hyperbolic).
+ * host_bytes must be at least the table size. Synchronous. */
+sar_status sar_plan_get_table(sar_plan_t plan, int32_t which, void* host_dst,
+                              size_t host_bytes);
+
+/* ---- batched execution (scenes of uneven size) ---- */
+
+/* Plan `n` scenes (params ps[0..n-1]) for one batched execution. */
+sar_status sar_batch_plan(const sar_params* ps, int32_t n, void* stream,
+                          sar_batch_t* out);
+
+/* Device workspace bytes for sar_batch_execute (sum over scenes). */
+size_t sar_batch_workspace_bytes(sar_batch_t batch);
+
+/* Run every scene: raw_dev[i] [Na_i][Nr_i] -> img_dev[i] (layout as in
+ * sar_rda_execute).  raw/img are host arrays of n device pointers; work_dev
+ * holds sar_batch_workspace_bytes(batch).  Asynchronous on `stream`. */
+sar_status sar_batch_execute(sar_batch_t batch, const void* const* raw_dev,
+                             void* const* img_dev, void* work_dev, void* stream);
+
+void sar_batch_destroy(sar_batch_t batch);
+
+/* Measure candidate kernel configurations for the plan's sizes on the
+ * current device and store the winners in a JSON cache at cache_path
+ * (NULL: $SAR_AUTOTUNE_CACHE).  Later plans read the cache. Synchronous. */
+sar_status sar_autotune(const sar_params* p, const char* cache_path);
+
+/* Message for the last non-OK status on the calling thread ("" if none). */
+const char* sar_last_error(void);
+
+/* Library version string. */
+const char* sar_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAR_RDA_H */

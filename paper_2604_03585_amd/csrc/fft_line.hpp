@@ -1,0 +1,240 @@
+// fft_line.hpp -- register/LDS line FFT building blocks for gfx950.
+//
+// One line of N complex64 points (64 <= N <= 16384, power of two) is held by
+// T = N/16 threads, 16 points per thread, in the "strided" register layout:
+//
+//     thread t, register m  <->  element t + m*T .
+//
+// The transform is a sequence of self-sorting (Stockham) passes: radix-16
+// passes followed by at most one radix-2/4/8 pass (N = 16^a * r).  A pass
+// with radix R and span Ns (product of the earlier radices) computes, for
+// every butterfly j in [0, N/R),
+//
+//     v_i = x[j + i*N/R] * W_{Ns*R}^{(j mod Ns)*i},   i = 0..R-1
+//     y[(j/Ns)*Ns*R + (j mod Ns) + k*Ns] = DFT_R(v)_k,
+//
+// and thread t owns butterflies j = t + q*T (q < 16/R), whose inputs are its
+// own registers q + i*(16/R).  Between passes the data go through LDS once
+// (scatter write, barrier, strided read).  The last pass writes y in natural
+// order straight back to the same registers, so a forward transform ends in
+// the layout in which the next step (filter multiply, inverse transform,
+// store) starts: FFT -> x H -> IFFT needs no extra exchange.
+//
+// The inverse transform (INV = true) uses conjugated twiddles and butterflies,
+// i.e. computes sum_k X[k] exp(+2 pi i k n / N) without the 1/N, which the
+// callers fold into the filter.  This equals the paper's conj(FFT(conj(.)))
+// form of the IFFT (Sec. II.C) up to rounding.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace sar {
+
+// ---------------------------------------------------------------- complex
+__device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 c_mul(float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 c_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 c_conj(float2 a) { return make_float2(a.x, -a.y); }
+
+// a * (-j) for the forward transform, a * (+j) for the inverse.
+template <bool INV>
+__device__ __forceinline__ float2 c_mul_mj(float2 a)
+{
+    return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// a * exp(-+ j pi/4) = a * (1 -+ j)/sqrt(2)
+template <bool INV>
+__device__ __forceinline__ float2 c_mul_w8(float2 a)
+{
+    constexpr float r = 0.70710678118654752440f;
+    return INV ? make_float2(r * (a.x - a.y), r * (a.y + a.x))
+               : make_float2(r * (a.x + a.y), r * (a.y - a.x));
+}
+
+// a * exp(-+ j 3pi/4) = a * (-1 -+ j)/sqrt(2)
+template <bool INV>
+__device__ __forceinline__ float2 c_mul_w8_3(float2 a)
+{
+    constexpr float r = 0.70710678118654752440f;
+    return INV ? make_float2(-r * (a.x + a.y), r * (a.x - a.y))
+               : make_float2(r * (a.y - a.x), -r * (a.x + a.y));
+}
+
+// a * (c, -+ s)
+template <bool INV>
+__device__ __forceinline__ float2 c_mul_cs(float2 a, float c, float s)
+{
+    return c_mul(a, make_float2(c, INV ? s : -s));
+}
+
+// ---------------------------------------------------------- small DFTs
+// All take natural-order input in v[] and leave natural-order output.
+template <bool INV>
+__device__ __forceinline__ void dft2(float2& a, float2& b)
+{
+    float2 t = a;
+    a = c_add(t, b);
+    b = c_sub(t, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3)
+{
+    float2 s0 = c_add(a0, a2), d0 = c_sub(a0, a2);
+    float2 s1 = c_add(a1, a3), d1 = c_mul_mj<INV>(c_sub(a1, a3));
+    a0 = c_add(s0, s1);
+    a2 = c_sub(s0, s1);
+    a1 = c_add(d0, d1);
+    a3 = c_sub(d0, d1);
+}
+
+template <int R, bool INV> struct Dft;
+
+template <bool INV> struct Dft<2, INV> {
+    __device__ __forceinline__ static void run(float2* v) { dft2<INV>(v[0], v[1]); }
+};
+
+template <bool INV> struct Dft<4, INV> {
+    __device__ __forceinline__ static void run(float2* v) { dft4<INV>(v[0], v[1], v[2], v[3]); }
+};
+
+// DFT8 = DFT2 (stride 4) x twiddle W8^{n2 k1} x DFT4.
+template <bool INV> struct Dft<8, INV> {
+    __device__ __forceinline__ static void run(float2* v)
+    {
+        dft2<INV>(v[0], v[4]);
+        dft2<INV>(v[1], v[5]);
+        dft2<INV>(v[2], v[6]);
+        dft2<INV>(v[3], v[7]);
+        v[5] = c_mul_w8<INV>(v[5]);
+        v[6] = c_mul_mj<INV>(v[6]);
+        v[7] = c_mul_w8_3<INV>(v[7]);
+        // y[n2][k1] sits in v[n2 + 4 k1]; DFT4 over n2 gives X[k1 + 2 k2]
+        float2 a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+        float2 b0 = v[4], b1 = v[5], b2 = v[6], b3 = v[7];
+        dft4<INV>(a0, a1, a2, a3);
+        dft4<INV>(b0, b1, b2, b3);
+        v[0] = a0; v[2] = a1; v[4] = a2; v[6] = a3;
+        v[1] = b0; v[3] = b1; v[5] = b2; v[7] = b3;
+    }
+};
+
+// DFT16 = DFT4 (stride 4) x twiddle W16^{n2 k1} x DFT4.
+template <bool INV> struct Dft<16, INV> {
+    __device__ __forceinline__ static void run(float2* v)
+    {
+        constexpr float c1 = 0.92387953251128675613f;   // cos(pi/8)
+        constexpr float s1 = 0.38268343236508977173f;   // sin(pi/8)
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) dft4<INV>(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
+        // y[n2][k1] is in v[n2 + 4 k1]
+        v[5] = c_mul_cs<INV>(v[5], c1, s1);     // n2=1 k1=1: W16^1
+        v[9] = c_mul_w8<INV>(v[9]);             // n2=1 k1=2: W16^2
+        v[13] = c_mul_cs<INV>(v[13], s1, c1);   // n2=1 k1=3: W16^3
+        v[6] = c_mul_w8<INV>(v[6]);             // n2=2 k1=1: W16^2
+        v[10] = c_mul_mj<INV>(v[10]);           // n2=2 k1=2: W16^4
+        v[14] = c_mul_w8_3<INV>(v[14]);         // n2=2 k1=3: W16^6
+        v[7] = c_mul_cs<INV>(v[7], s1, c1);     // n2=3 k1=1: W16^3
+        v[11] = c_mul_w8_3<INV>(v[11]);         // n2=3 k1=2: W16^6
+        v[15] = c_mul_cs<INV>(v[15], -c1, -s1); // n2=3 k1=3: W16^9 = (-c1, +s1)
+        float2 o[16];
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            float2 a0 = v[4 * k1], a1 = v[4 * k1 + 1], a2 = v[4 * k1 + 2], a3 = v[4 * k1 + 3];
+            dft4<INV>(a0, a1, a2, a3);
+            o[k1] = a0; o[k1 + 4] = a1; o[k1 + 8] = a2; o[k1 + 12] = a3;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = o[i];
+    }
+};
+
+// ------------------------------------------------------------ pass plan
+__host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+template <int N> struct LineGeom {
+    static_assert(N >= 64 && N <= 16384 && (N & (N - 1)) == 0, "line length");
+    static constexpr int T = N / 16;                       // threads per line
+    static constexpr int LOG = ilog2(N);
+    static constexpr int N16 = LOG / 4;                    // radix-16 passes
+    static constexpr int REM = 1 << (LOG % 4);             // trailing radix (1 = none)
+    static constexpr int NP = N16 + (REM > 1 ? 1 : 0);     // number of passes
+    __host__ __device__ static constexpr int radix(int p) { return p < N16 ? 16 : REM; }
+    __host__ __device__ static constexpr int span(int p)   // Ns of pass p
+    {
+        return p == 0 ? 1 : span(p - 1) * radix(p - 1);
+    }
+    // offset of pass p's twiddles in the per-N table (pass 0 has none)
+    __host__ __device__ static constexpr int tw_off(int p)
+    {
+        return p <= 1 ? 0 : tw_off(p - 1) + (radix(p - 1) - 1) * span(p - 1);
+    }
+    static constexpr int TW_SIZE = tw_off(NP);
+    // LDS words (float2) per line: one pad slot every 16 entries
+    static constexpr int LDS = N + N / 16;
+};
+
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+
+// One Stockham pass P of an N-point line (see the header comment).
+// `tw` points at this N's twiddle table: for pass p, entry
+// tw_off(p) + (i-1)*Ns + jm holds exp(-2 pi i * jm * i / (Ns * R)).
+template <int N, int P, bool INV>
+__device__ __forceinline__ void fft_pass(float2 (&x)[16], float2* __restrict__ lds,
+                                         const float2* __restrict__ tw, int t)
+{
+    using G = LineGeom<N>;
+    constexpr int R = G::radix(P);
+    constexpr int NS = G::span(P);
+    constexpr int B = 16 / R;
+    constexpr bool LAST = (P == G::NP - 1);
+    constexpr int OFF = G::tw_off(P);
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+        float2 v[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = x[q + i * B];
+        const int j = t + q * G::T;
+        const int jm = j & (NS - 1);
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int i = 1; i < R; ++i) {
+                float2 w = tw[OFF + (i - 1) * NS + jm];
+                if (INV) w.y = -w.y;
+                v[i] = c_mul(v[i], w);
+            }
+        }
+        Dft<R, INV>::run(v);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int i = 0; i < R; ++i) x[q + i * B] = v[i];
+        } else {
+            const int base = (j / NS) * NS * R + jm;
+#pragma unroll
+            for (int i = 0; i < R; ++i) lds[lds_pad(base + i * NS)] = v[i];
+        }
+    }
+    if constexpr (!LAST) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 16; ++m) x[m] = lds[lds_pad(t + m * G::T)];
+        __syncthreads();
+    }
+}
+
+template <int N, bool INV, int P = 0>
+__device__ __forceinline__ void fft_line(float2 (&x)[16], float2* __restrict__ lds,
+                                         const float2* __restrict__ tw, int t)
+{
+    if constexpr (P < LineGeom<N>::NP) {
+        fft_pass<N, P, INV>(x, lds, tw, t);
+        fft_line<N, INV, P + 1>(x, lds, tw, t);
+    }
+}
+
+}  // namespace sar

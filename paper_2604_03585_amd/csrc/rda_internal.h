@@ -1,0 +1,49 @@
+// rda_internal.h -- declarations shared by the host API and the kernel
+// launchers inside libsar_rda.so (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "sar_rda.h"
+
+namespace sar {
+
+// Record a message for sar_last_error() on this thread and return `st`.
+sar_status set_error(sar_status st, const char* fmt, ...);
+void clear_error();
+
+enum class LineOp { Fused, Forward, Inverse, RcmcAz };
+
+// Host-side description of the hyperbolic azimuth tables and RCMC kernel.
+struct RcmcHost {
+    const double* stretch;   // device, Na doubles: 1/D_k - 1
+    const double* rate;      // device, Na doubles: 2 D_k / lambda
+    double r_near;
+    double beta;
+    int taps;                // 0 or 8
+    int nr;                  // range lines (rows of the [Nr][Na] data)
+};
+
+// Line kernels for line length n in {64, ..., 16384}.
+//  Fused:   out = IFFT(FFT(in) * H)   (H includes 1/n)
+//  Forward: out = FFT(in) * scale;  Inverse: out = unscaled IFFT(in) * scale
+//  RcmcAz:  out[n] = IFFT(RCMC(in)[n] * phase / n), rh required, lines = rh->nr
+hipError_t launch_line(LineOp op, int n, const void* in, void* out, int lines, const void* H,
+                       const void* tw, float scale, const RcmcHost* rh, hipStream_t s);
+int twiddle_table_size(int n);
+
+hipError_t launch_rowmul(const void* in, void* out, int rows, int n, const void* H, hipStream_t s);
+hipError_t launch_corner_turn(const void* in, void* out, int rows, int cols, hipStream_t s);
+hipError_t launch_rcmc_interp(const void* A, void* out, int na, const RcmcHost& rh, hipStream_t s);
+hipError_t launch_az_phase(const void* in, void* out, int na, const RcmcHost& rh, float scale,
+                           hipStream_t s);
+
+hipError_t launch_gen_twiddles(void* tw, int n, hipStream_t s);
+hipError_t launch_gen_chirp_filter(void* H, int n, int len, double K, int sign, double scale,
+                                   hipStream_t s);
+hipError_t launch_gen_hyper_tables(double* stretch, double* rate, int na, double lam, double v,
+                                   hipStream_t s);
+
+}  // namespace sar

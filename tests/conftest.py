@@ -16,6 +16,21 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: long-running CPU test")
 
 
+def pytest_collection_modifyitems(config, items):
+    gpu_items = [i for i in items if "gpu" in i.keywords]
+    if not gpu_items:
+        return
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except Exception:  # pragma: no cover
+        has_gpu = False
+    if not has_gpu:
+        skip = pytest.mark.skip(reason="needs a GPU")
+        for i in gpu_items:
+            i.add_marker(skip)
+
+
 @pytest.fixture(scope="session")
 def oracle_lib():
     from oracle import oracle as O
