@@ -15,7 +15,8 @@ import os
 import re
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsar_rda.so")
+# SAR_RDA_LIB selects another build of the same library (same ABI).
+LIB_PATH = os.environ.get("SAR_RDA_LIB") or os.path.join(_HERE, "libsar_rda.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "sar_rda.h")
 
 # torch is imported first: ROCm builds of PyTorch carry their own HIP runtime
@@ -49,7 +50,8 @@ SAR_AZ_LFM, SAR_AZ_HYPERBOLIC = 0, 1
 SAR_FP32, SAR_SPLIT_FP16, SAR_SPLIT_BF16 = 0, 1, 2
 SAR_FUSED, SAR_UNFUSED = 0, 1
 
-TABLE_HR, TABLE_HA, TABLE_STRETCH, TABLE_RATE = 0, 1, 2, 3
+TABLE_HR, TABLE_HA, TABLE_STRETCH, TABLE_RATE, TABLE_RCMC = 0, 1, 2, 3, 4
+RCMC_INTERVALS = 64
 
 
 class sar_params(ctypes.Structure):
@@ -240,6 +242,8 @@ def sar_plan_get_table(plan, which: int):
         out = np.empty(nr, np.complex64)
     elif which == TABLE_HA:
         out = np.empty(na, np.complex64)
+    elif which == TABLE_RCMC:
+        out = np.empty(8 * 4 * RCMC_INTERVALS, np.float32)
     else:
         out = np.empty(na, np.float64)
     _check(_sar_plan_get_table(plan, which, out.ctypes.data, out.nbytes), "sar_plan_get_table")

@@ -48,14 +48,15 @@ COMMON = [
 DEVICE_ONLY = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
+def sources(csrc: str = CSRC):
+    return sorted(os.path.join(csrc, f) for f in os.listdir(csrc)
                   if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, *DEVICE_ONLY, "-c", src, "-o", obj]
+def _compile(src: str, build_dir: str = BUILD) -> str:
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+    inc = ["-I", os.path.dirname(src)]
+    cmd = [HIPCC, *COMMON, *inc, *DEVICE_ONLY, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -69,12 +70,14 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = sources()
+def build(verbose: bool = False, csrc: str = CSRC, lib: str = LIB,
+          build_dir: str = BUILD) -> str:
+    """Compile every source of `csrc` and link `lib` (defaults: this package)."""
+    os.makedirs(build_dir, exist_ok=True)
+    srcs = sources(csrc)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda f: _compile(f, build_dir), srcs))
+    tmp = lib + ".tmp"
     rt = hip_runtime_dir()
     cmd = [CLANG, "-shared", "-fPIC", *objs, "-o", tmp,
            f"-L{rt}", "-l:libamdhip64.so", f"-Wl,-rpath,{rt}", "-Wl,--no-undefined",
@@ -82,10 +85,10 @@ def build(verbose: bool = False) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 if __name__ == "__main__":

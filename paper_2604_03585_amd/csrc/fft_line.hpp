@@ -1,20 +1,21 @@
 // fft_line.hpp -- register/LDS line FFT building blocks for gfx950.
 //
 // One line of N complex64 points (64 <= N <= 16384, power of two) is held by
-// T = N/16 threads, 16 points per thread, in the "strided" register layout:
+// T = N/E threads, E points per thread (E = 8 or 16), in the "strided"
+// register layout:
 //
 //     thread t, register m  <->  element t + m*T .
 //
-// The transform is a sequence of self-sorting (Stockham) passes: radix-16
-// passes followed by at most one radix-2/4/8 pass (N = 16^a * r).  A pass
-// with radix R and span Ns (product of the earlier radices) computes, for
-// every butterfly j in [0, N/R),
+// The transform is a sequence of self-sorting (Stockham) passes: radix-E
+// passes followed by at most one smaller power-of-two pass (N = E^a * r).
+// A pass with radix R and span Ns (product of the earlier radices) computes,
+// for every butterfly j in [0, N/R),
 //
 //     v_i = x[j + i*N/R] * W_{Ns*R}^{(j mod Ns)*i},   i = 0..R-1
 //     y[(j/Ns)*Ns*R + (j mod Ns) + k*Ns] = DFT_R(v)_k,
 //
-// and thread t owns butterflies j = t + q*T (q < 16/R), whose inputs are its
-// own registers q + i*(16/R).  Between passes the data go through LDS once
+// and thread t owns butterflies j = t + q*T (q < E/R), whose inputs are its
+// own registers q + i*(E/R).  Between passes the data go through LDS once
 // (scatter write, barrier, strided read).  The last pass writes y in natural
 // order straight back to the same registers, so a forward transform ends in
 // the layout in which the next step (filter multiply, inverse transform,
@@ -157,14 +158,21 @@ template <bool INV> struct Dft<16, INV> {
 // ------------------------------------------------------------ pass plan
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
-template <int N> struct LineGeom {
+// Points per thread for a line of length N.  16 (radix-16 passes) needs one
+// LDS exchange fewer per transform than 8 at N = 4096 and measured faster.
+__host__ __device__ constexpr int line_e(int n) { return n > 0 ? 16 : 16; }
+
+template <int N, int E = line_e(N)> struct LineGeom {
     static_assert(N >= 64 && N <= 16384 && (N & (N - 1)) == 0, "line length");
-    static constexpr int T = N / 16;                       // threads per line
+    static_assert(E == 8 || E == 16, "points per thread");
+    static_assert(N / E <= 1024, "threads per line");
+    static constexpr int T = N / E;                        // threads per line
     static constexpr int LOG = ilog2(N);
-    static constexpr int N16 = LOG / 4;                    // radix-16 passes
-    static constexpr int REM = 1 << (LOG % 4);             // trailing radix (1 = none)
-    static constexpr int NP = N16 + (REM > 1 ? 1 : 0);     // number of passes
-    __host__ __device__ static constexpr int radix(int p) { return p < N16 ? 16 : REM; }
+    static constexpr int RLOG = ilog2(E);
+    static constexpr int NFULL = LOG / RLOG;               // radix-E passes
+    static constexpr int REM = 1 << (LOG % RLOG);          // trailing radix (1 = none)
+    static constexpr int NP = NFULL + (REM > 1 ? 1 : 0);   // number of passes
+    __host__ __device__ static constexpr int radix(int p) { return p < NFULL ? E : REM; }
     __host__ __device__ static constexpr int span(int p)   // Ns of pass p
     {
         return p == 0 ? 1 : span(p - 1) * radix(p - 1);
@@ -181,19 +189,65 @@ template <int N> struct LineGeom {
 
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
 
-// One Stockham pass P of an N-point line (see the header comment).
-// `tw` points at this N's twiddle table: for pass p, entry
-// tw_off(p) + (i-1)*Ns + jm holds exp(-2 pi i * jm * i / (Ns * R)).
-template <int N, int P, bool INV>
-__device__ __forceinline__ void fft_pass(float2 (&x)[16], float2* __restrict__ lds,
-                                         const float2* __restrict__ tw, int t)
+// Twiddles a thread needs in pass P: for butterfly q (j = t + q*T) and
+// i = 1..R-1, exp(-2 pi i * (j mod Ns) * i / (Ns * R)), read from this N's
+// table (entry tw_off(P) + (i-1)*Ns + (j mod Ns)); passes with Ns == 1 need
+// none.
+template <int N, int P> struct PassTw {
+    using G = LineGeom<N>;
+    static constexpr bool ANY = P < G::NP && G::span(P) > 1;
+    static constexpr int COUNT = ANY ? (line_e(N) / G::radix(P)) * (G::radix(P) - 1) : 1;
+    float2 w[COUNT];
+};
+
+template <int N, int P>
+__device__ __forceinline__ void load_tw(PassTw<N, P>& pt, const float2* __restrict__ tw, int t)
 {
     using G = LineGeom<N>;
+    if constexpr (PassTw<N, P>::ANY && G::radix(P) == 16) {
+        // Radix-16 pass: W^1 and W^4 come from the table, the other powers are
+        // products (at most four roundings deep, ~3e-7 relative).  Thirteen
+        // complex products replace thirteen table reads: the fused kernel is
+        // bound by vector-memory issue, not by VALU.
+        constexpr int NS = G::span(P), B = line_e(N) / 16, OFF = G::tw_off(P);
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const int jm = (t + q * G::T) & (NS - 1);
+            float2* w = pt.w + q * 15;          // w[i-1] = W^i
+            w[0] = tw[OFF + jm];
+            w[3] = tw[OFF + 3 * NS + jm];
+            w[1] = c_mul(w[0], w[0]);
+            w[2] = c_mul(w[1], w[0]);
+            w[4] = c_mul(w[3], w[0]);
+            w[5] = c_mul(w[3], w[1]);
+            w[6] = c_mul(w[3], w[2]);
+            w[7] = c_mul(w[3], w[3]);
+#pragma unroll
+            for (int i = 8; i < 15; ++i) w[i] = c_mul(w[7], w[i - 8]);
+        }
+    } else if constexpr (PassTw<N, P>::ANY) {
+        constexpr int R = G::radix(P), NS = G::span(P), B = line_e(N) / R, OFF = G::tw_off(P);
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const int jm = (t + q * G::T) & (NS - 1);
+#pragma unroll
+            for (int i = 1; i < R; ++i) pt.w[q * (R - 1) + i - 1] = tw[OFF + (i - 1) * NS + jm];
+        }
+    }
+}
+
+// One Stockham pass P of an N-point line (see the header comment), with its
+// twiddles already loaded.
+template <int N, int P, bool INV>
+__device__ __forceinline__ void fft_pass(float2 (&x)[line_e(N)], float2* __restrict__ lds,
+                                         const PassTw<N, P>& pt, int t)
+{
+    using G = LineGeom<N>;
+    constexpr int E = line_e(N);
     constexpr int R = G::radix(P);
     constexpr int NS = G::span(P);
-    constexpr int B = 16 / R;
+    constexpr int B = E / R;
     constexpr bool LAST = (P == G::NP - 1);
-    constexpr int OFF = G::tw_off(P);
 #pragma unroll
     for (int q = 0; q < B; ++q) {
         float2 v[R];
@@ -204,7 +258,7 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[16], float2* __restrict__ l
         if constexpr (NS > 1) {
 #pragma unroll
             for (int i = 1; i < R; ++i) {
-                float2 w = tw[OFF + (i - 1) * NS + jm];
+                float2 w = pt.w[q * (R - 1) + i - 1];
                 if (INV) w.y = -w.y;
                 v[i] = c_mul(v[i], w);
             }
@@ -222,19 +276,36 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[16], float2* __restrict__ l
     if constexpr (!LAST) {
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < 16; ++m) x[m] = lds[lds_pad(t + m * G::T)];
+        for (int m = 0; m < E; ++m) x[m] = lds[lds_pad(t + m * G::T)];
         __syncthreads();
     }
 }
 
-template <int N, bool INV, int P = 0>
-__device__ __forceinline__ void fft_line(float2 (&x)[16], float2* __restrict__ lds,
-                                         const float2* __restrict__ tw, int t)
+// Passes P.. of the line.  `before_last` runs just before the last pass
+// (callers use it to request data needed right after the transform, e.g.
+// the matched filter, so that its latency overlaps the last pass).
+struct NoOp {
+    __device__ __forceinline__ void operator()() const {}
+};
+
+template <int N, bool INV, int P, class F>
+__device__ __forceinline__ void fft_from(float2 (&x)[line_e(N)], float2* __restrict__ lds,
+                                         const float2* __restrict__ tw, int t, F&& before_last)
 {
     if constexpr (P < LineGeom<N>::NP) {
-        fft_pass<N, P, INV>(x, lds, tw, t);
-        fft_line<N, INV, P + 1>(x, lds, tw, t);
+        if constexpr (P == LineGeom<N>::NP - 1) before_last();
+        PassTw<N, P> cur;
+        load_tw<N, P>(cur, tw, t);
+        fft_pass<N, P, INV>(x, lds, cur, t);
+        fft_from<N, INV, P + 1>(x, lds, tw, t, before_last);
     }
+}
+
+template <int N, bool INV, class F = NoOp>
+__device__ __forceinline__ void fft_line(float2 (&x)[line_e(N)], float2* __restrict__ lds,
+                                         const float2* __restrict__ tw, int t, F&& before_last = F())
+{
+    fft_from<N, INV, 0>(x, lds, tw, t, before_last);
 }
 
 }  // namespace sar

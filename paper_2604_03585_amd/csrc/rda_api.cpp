@@ -92,6 +92,8 @@ struct sar_plan_s {
     float2* Ha = nullptr;         // LFM azimuth filter, includes 1/Na
     double* stretch = nullptr;    // hyperbolic: 1/D - 1
     double* rate = nullptr;       // hyperbolic: 2 D / lambda
+    float* rcmc_tab = nullptr;    // hyperbolic: interpolation weight coefficients
+    double stretch_max = 0.0;     // hyperbolic: 1/D - 1 at |f| = 1/2
 };
 
 namespace {
@@ -156,7 +158,8 @@ sar_status check_ptr(const void* p, const char* name)
 
 sar::RcmcHost rcmc_host(const sar_plan_s* P)
 {
-    return sar::RcmcHost{P->stretch, P->rate, P->p.r_near, P->p.rcmc_beta, P->p.rcmc_taps, P->p.Nr};
+    return sar::RcmcHost{P->stretch, P->rate, P->rcmc_tab, P->p.r_near,
+                         P->stretch_max, P->p.rcmc_taps, P->p.Nr};
 }
 
 using sar::LineOp;
@@ -251,6 +254,7 @@ sar_status sar_plan(const sar_params* p, void* stream, sar_plan_t* out)
     const size_t o_ha = off;  off = align_up(off + (hyper ? 0 : sizeof(float2) * (size_t)Na), A);
     const size_t o_st = off;  off = align_up(off + (hyper ? sizeof(double) * (size_t)Na : 0), A);
     const size_t o_rt = off;  off = align_up(off + (hyper ? sizeof(double) * (size_t)Na : 0), A);
+    const size_t o_tb = off;  off = align_up(off + (hyper ? sizeof(float) * (size_t)sar::rcmc_table_floats() : 0), A);
     e = hipMalloc(&P->block, off);
     if (e != hipSuccess) {
         delete P;
@@ -263,6 +267,12 @@ sar_status sar_plan(const sar_params* p, void* stream, sar_plan_t* out)
     P->Ha = hyper ? nullptr : (float2*)(b + o_ha);
     P->stretch = hyper ? (double*)(b + o_st) : nullptr;
     P->rate = hyper ? (double*)(b + o_rt) : nullptr;
+    P->rcmc_tab = hyper ? (float*)(b + o_tb) : nullptr;
+    if (hyper) {
+        const double x = p->lambda * 0.5 / (2.0 * p->v);
+        const double D = std::sqrt(1.0 - x * x);
+        P->stretch_max = x * x / (D * (1.0 + D));
+    }
 
     auto cleanup_fail = [&](sar_status code) {
         (void)hipFree(P->block);
@@ -282,6 +292,8 @@ sar_status sar_plan(const sar_params* p, void* stream, sar_plan_t* out)
     } else {
         if ((e = sar::launch_gen_hyper_tables(P->stretch, P->rate, Na, p->lambda, p->v, s)) != hipSuccess)
             return cleanup_fail(hip_fail(e, "hyperbolic table generator"));
+        if ((e = sar::launch_gen_rcmc_table(P->rcmc_tab, p->rcmc_beta, s)) != hipSuccess)
+            return cleanup_fail(hip_fail(e, "RCMC weight table generator"));
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup_fail(hip_fail(e, "plan synchronisation"));
     *out = P;
@@ -434,6 +446,7 @@ sar_status sar_plan_get_table(sar_plan_t P, int32_t which, void* host, size_t by
     case 1: src = P->Ha; need = sizeof(float2) * (size_t)P->p.Na; break;
     case 2: src = P->stretch; need = sizeof(double) * (size_t)P->p.Na; break;
     case 3: src = P->rate; need = sizeof(double) * (size_t)P->p.Na; break;
+    case 4: src = P->rcmc_tab; need = sizeof(float) * (size_t)sar::rcmc_table_floats(); break;
     default: return fail(SAR_ERR_BAD_PARAM, "table %d unknown", which);
     }
     if (!src) return fail(SAR_ERR_BAD_PARAM, "table %d does not exist for this azimuth model", which);

@@ -20,8 +20,9 @@ enum class LineOp { Fused, Forward, Inverse, RcmcAz };
 struct RcmcHost {
     const double* stretch;   // device, Na doubles: 1/D_k - 1
     const double* rate;      // device, Na doubles: 2 D_k / lambda
+    const float* table;      // device, rcmc_table_floats() weight coefficients
     double r_near;
-    double beta;
+    double stretch_max;      // largest stretch_k (at |f| = 1/2)
     int taps;                // 0 or 8
     int nr;                  // range lines (rows of the [Nr][Na] data)
 };
@@ -43,6 +44,8 @@ hipError_t launch_az_phase(const void* in, void* out, int na, const RcmcHost& rh
 hipError_t launch_gen_twiddles(void* tw, int n, hipStream_t s);
 hipError_t launch_gen_chirp_filter(void* H, int n, int len, double K, int sign, double scale,
                                    hipStream_t s);
+hipError_t launch_gen_rcmc_table(float* tab, double beta, hipStream_t s);
+int rcmc_table_floats();
 hipError_t launch_gen_hyper_tables(double* stretch, double* rate, int na, double lam, double v,
                                    hipStream_t s);
 

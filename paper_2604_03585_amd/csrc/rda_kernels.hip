@@ -36,17 +36,19 @@ __device__ __forceinline__ float2 twiddle_fp64(long long num, long long den)
     return make_float2((float)c, (float)s);
 }
 
-// Per-N Stockham twiddle table (layout in fft_line.hpp, LineGeom::tw_off).
-__global__ void k_gen_twiddles(float2* __restrict__ tw, int n)
+// Per-N Stockham twiddle table (layout in fft_line.hpp, LineGeom::tw_off),
+// for radix-E passes followed by one smaller pass.
+__global__ void k_gen_twiddles(float2* __restrict__ tw, int n, int e_pts)
 {
-    int log = 0;
+    int log = 0, rlog = 0;
     while ((1 << log) < n) ++log;
-    const int n16 = log / 4, rem = 1 << (log % 4);
-    const int np = n16 + (rem > 1 ? 1 : 0);
+    while ((1 << rlog) < e_pts) ++rlog;
+    const int nfull = log / rlog, rem = 1 << (log % rlog);
+    const int np = nfull + (rem > 1 ? 1 : 0);
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     int off = 0, ns = 1;
     for (int p = 0; p < np; ++p) {
-        const int R = p < n16 ? 16 : rem;
+        const int R = p < nfull ? e_pts : rem;
         if (p >= 1) {
             const int cnt = (R - 1) * ns;
             if (e >= off && e < off + cnt) {
@@ -116,67 +118,60 @@ __device__ __forceinline__ int xcd_group(int b, int groups)
 }
 
 template <int N>
-__device__ __forceinline__ void load_line(float2 (&x)[16], const float2* __restrict__ src, int t)
+__device__ __forceinline__ void load_line(float2 (&x)[line_e(N)], const float2* __restrict__ src,
+                                          int t)
 {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) x[m] = src[t + m * LineGeom<N>::T];
+    for (int m = 0; m < line_e(N); ++m) x[m] = src[t + m * LineGeom<N>::T];
 }
 
 template <int N>
-__device__ __forceinline__ void store_line(const float2 (&x)[16], float2* __restrict__ dst, int t)
+__device__ __forceinline__ void store_line(const float2 (&x)[line_e(N)], float2* __restrict__ dst,
+                                           int t)
 {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) dst[t + m * LineGeom<N>::T] = x[m];
+    for (int m = 0; m < line_e(N); ++m) dst[t + m * LineGeom<N>::T] = x[m];
 }
 
-template <int N>
+// One workgroup per group of LPW lines.
+enum LineKind { LK_FUSED = 0, LK_FWD = 1, LK_INV = 2 };
+
+//  LK_FUSED: out = IFFT(FFT(in) * H)      (H carries the 1/N)
+//  LK_FWD:   out = FFT(in) * scale;  LK_INV: out = IFFT_unscaled(in) * scale
+template <int N, int KIND>
 __global__ __launch_bounds__(LineLaunch<N>::BLOCK) void
-k_line_fused(const float2* in, float2* out, int lines, const float2* __restrict__ H,
-             const float2* __restrict__ tw)
+k_line(const float2* in, float2* out, int lines, const float2* __restrict__ H,
+       const float2* __restrict__ tw, float scale)
 {
     using L = LineLaunch<N>;
+    constexpr int E = line_e(N);
     extern __shared__ float2 smem[];
-    const int groups = (lines + L::LPW - 1) / L::LPW;
-    const int g = xcd_group(blockIdx.x, groups);
     const int sub = threadIdx.x / L::T, t = threadIdx.x % L::T;
-    const int line = g * L::LPW + sub;
+    const int line = blockIdx.x * L::LPW + sub;
     const bool live = line < lines;
     float2* lds = smem + sub * LineGeom<N>::LDS;
-    float2 x[16];
+    float2 x[E];
     if (live) load_line<N>(x, in + (size_t)line * N, t);
     else {
 #pragma unroll
-        for (int m = 0; m < 16; ++m) x[m] = make_float2(0.f, 0.f);
+        for (int m = 0; m < E; ++m) x[m] = make_float2(0.f, 0.f);
     }
-    fft_line<N, false>(x, lds, tw, t);
+    if constexpr (KIND == LK_FUSED) {
+        // the filter is requested just before the last forward pass
+        float2 h[E];
+        fft_line<N, false>(x, lds, tw, t, [&] {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) x[m] = c_mul(x[m], H[t + m * L::T]);
-    fft_line<N, true>(x, lds, tw, t);
-    if (live) store_line<N>(x, out + (size_t)line * N, t);
-}
-
-template <int N, bool INV>
-__global__ __launch_bounds__(LineLaunch<N>::BLOCK) void
-k_line_fft(const float2* in, float2* out, int lines, const float2* __restrict__ tw, float scale)
-{
-    using L = LineLaunch<N>;
-    extern __shared__ float2 smem[];
-    const int groups = (lines + L::LPW - 1) / L::LPW;
-    const int g = xcd_group(blockIdx.x, groups);
-    const int sub = threadIdx.x / L::T, t = threadIdx.x % L::T;
-    const int line = g * L::LPW + sub;
-    const bool live = line < lines;
-    float2* lds = smem + sub * LineGeom<N>::LDS;
-    float2 x[16];
-    if (live) load_line<N>(x, in + (size_t)line * N, t);
-    else {
+            for (int m = 0; m < E; ++m) h[m] = H[t + m * L::T];
+        });
 #pragma unroll
-        for (int m = 0; m < 16; ++m) x[m] = make_float2(0.f, 0.f);
-    }
-    fft_line<N, INV>(x, lds, tw, t);
-    if (scale != 1.0f) {
+        for (int m = 0; m < E; ++m) x[m] = c_mul(x[m], h[m]);
+        fft_line<N, true>(x, lds, tw, t);
+    } else {
+        fft_line<N, KIND == LK_INV>(x, lds, tw, t);
+        if (scale != 1.0f) {
 #pragma unroll
-        for (int m = 0; m < 16; ++m) x[m] = c_scale(x[m], scale);
+            for (int m = 0; m < E; ++m) x[m] = c_scale(x[m], scale);
+        }
     }
     if (live) store_line<N>(x, out + (size_t)line * N, t);
 }
@@ -224,102 +219,262 @@ __global__ __launch_bounds__(256) void k_corner_turn(const float2* __restrict__ 
 }
 
 // ===================================================== RCMC
-// Interpolation weights of the 8-tap Kaiser-windowed sinc (taps t = -3..4
-// about floor(p), x = p - floor(p)), in a division-free form: with
-// z_t = t - x, sinc(z_t) = -(-1)^t sin(pi x) / (pi z_t), so after the unit-sum
-// normalisation the weights are proportional to
-//     q_t = (-1)^t * Win(z_t) * prod_{t' != t} z_t',
-//     Win(z) = I0(beta * sqrt(1 - z^2/16)) = sum_k u^k / (k!)^2,
-//     u = (beta^2 / 4) (1 - z^2 / 16),
-// which also collapses to the identity at x = 0 with no special case.
-// Returns sum_t q_t * a_t / sum_t q_t for the eight samples a[].
-__device__ __forceinline__ float2 kaiser_sinc8(float x, float b4, float b64, const float2 (&a)[8])
+// The 8-tap Kaiser-windowed sinc (taps t = -3..4 about floor(p), x = p -
+// floor(p), weights normalised to unit sum) depends on x alone.  Its eight
+// weight functions w_t(x) are smooth on [0, 1), so the plan stores them as
+// piecewise cubics: RCMC_INTERVALS intervals, on each a degree-3 Chebyshev
+// interpolant of the exact FP64 weights, in monomial form in the local
+// variable u = x * RCMC_INTERVALS - b in [0, 1].  Layout (coefficient-major,
+// so that lanes with different intervals hit different LDS banks):
+//     tab[(t * 4 + j) * RCMC_INTERVALS + b] = coefficient of u^j, tap t.
+// The interpolation error is below 1e-7 of the weights (tested against the
+// oracle's weights); the kernels copy the 8 KiB table into LDS.
+constexpr int RCMC_INTERVALS = 64;
+constexpr int RCMC_TAB = 8 * 4 * RCMC_INTERVALS;
+
+__device__ double i0_fp64(double y)
 {
-    float z[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) z[i] = (float)(i - 3) - x;
-    float pre[8], suf[8];
-    pre[0] = 1.0f;
-#pragma unroll
-    for (int i = 1; i < 8; ++i) pre[i] = pre[i - 1] * z[i - 1];
-    suf[7] = 1.0f;
-#pragma unroll
-    for (int i = 6; i >= 0; --i) suf[i] = suf[i + 1] * z[i + 1];
-    float den = 0.0f;
-    float2 acc = make_float2(0.0f, 0.0f);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const float u = fmaf(-b64, z[i] * z[i], b4);
-        // Horner of sum_{k=0}^{8} u^k / (k!)^2
-        float w = 1.0f / 1625702400.0f;
-        w = fmaf(w, u, 1.0f / 25401600.0f);
-        w = fmaf(w, u, 1.0f / 518400.0f);
-        w = fmaf(w, u, 1.0f / 14400.0f);
-        w = fmaf(w, u, 1.0f / 576.0f);
-        w = fmaf(w, u, 1.0f / 36.0f);
-        w = fmaf(w, u, 0.25f);
-        w = fmaf(w, u, 1.0f);
-        w = fmaf(w, u, 1.0f);
-        float q = w * pre[i] * suf[i];
-        if ((i - 3) & 1) q = -q;
-        den += q;
-        acc.x = fmaf(q, a[i].x, acc.x);
-        acc.y = fmaf(q, a[i].y, acc.y);
+    const double q = 0.25 * y * y;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 200; ++k) {
+        term *= q / ((double)k * (double)k);
+        sum += term;
+        if (term < 1e-17 * sum) break;
     }
-    const float inv = 1.0f / den;
-    return make_float2(acc.x * inv, acc.y * inv);
+    return sum;
+}
+
+// Exact normalised weights at x (FP64): K(z) = sinc(z) I0(beta sqrt(1-(z/4)^2)).
+__device__ void kaiser_weights_fp64(double x, double beta, double* w)
+{
+    double sum = 0.0;
+    for (int i = 0; i < 8; ++i) {
+        const double z = (double)(i - 3) - x;
+        const double r = z / 4.0;
+        const double sc = (z == 0.0) ? 1.0 : sinpi(z) / (3.14159265358979323846 * z);
+        const double arg = 1.0 - r * r;
+        w[i] = (arg > 0.0 ? sc * i0_fp64(beta * sqrt(arg)) : 0.0);
+        sum += w[i];
+    }
+    for (int i = 0; i < 8; ++i) w[i] /= sum;
+}
+
+// One thread per interval b: Chebyshev nodes, exact weights, 4x4 solve.
+__global__ void k_gen_rcmc_table(float* __restrict__ tab, double beta)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= RCMC_INTERVALS) return;
+    double u[4], w[4][8];
+    for (int j = 0; j < 4; ++j) {
+        u[j] = 0.5 * (1.0 + cospi((2.0 * j + 1.0) / 8.0));
+        kaiser_weights_fp64(((double)b + u[j]) / RCMC_INTERVALS, beta, w[j]);
+    }
+    for (int t = 0; t < 8; ++t) {
+        double M[4][5];
+        for (int j = 0; j < 4; ++j) {
+            double pw = 1.0;
+            for (int p = 0; p < 4; ++p) { M[j][p] = pw; pw *= u[j]; }
+            M[j][4] = w[j][t];
+        }
+        for (int c = 0; c < 4; ++c) {             // Gaussian elimination, partial pivot
+            int piv = c;
+            for (int r = c + 1; r < 4; ++r)
+                if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+            for (int q = 0; q < 5; ++q) { double tmp = M[c][q]; M[c][q] = M[piv][q]; M[piv][q] = tmp; }
+            for (int r = c + 1; r < 4; ++r) {
+                const double f = M[r][c] / M[c][c];
+                for (int q = c; q < 5; ++q) M[r][q] -= f * M[c][q];
+            }
+        }
+        double cf[4];
+        for (int c = 3; c >= 0; --c) {
+            double acc = M[c][4];
+            for (int q = c + 1; q < 4; ++q) acc -= M[c][q] * cf[q];
+            cf[c] = acc / M[c][c];
+        }
+        for (int j = 0; j < 4; ++j) tab[(t * 4 + j) * RCMC_INTERVALS + b] = (float)cf[j];
+    }
 }
 
 struct RcmcArgs {
     const double* stretch;   // 1/D_k - 1 per Doppler bin
     const double* rate;      // 2 D_k / lambda per Doppler bin
+    const float* table;      // RCMC_TAB weight coefficients (global)
     double r_near;
-    float b4, b64;           // beta^2/4, beta^2/64
+    double stretch_max;      // max_k stretch_k (|f| = 1/2)
     int nr;
 };
 
-// RCMC output sample y[n][k] from range-Doppler A[Nr][Na] (rows outside
-// [0, Nr) contribute nothing), times exp(+j 2 pi frac(R0 * rate_k)) * scale.
-template <int TAPS>
-__device__ __forceinline__ float2 rcmc_sample(const float2* __restrict__ A, int na, int n, int k,
-                                              const RcmcArgs& ra, float scale, bool phase)
+__device__ __forceinline__ void load_rcmc_table(float* __restrict__ lds_tab,
+                                                const float* __restrict__ tab, int tid, int nthreads)
 {
-    const double R0 = ra.r_near + (double)n;
-    float2 y;
-    if constexpr (TAPS == 0) {
-        y = A[(size_t)n * na + k];
+    for (int i = tid; i < RCMC_TAB; i += nthreads) lds_tab[i] = tab[i];
+}
+
+// sum_t w_t(x) a_t with the weights from the LDS table.
+__device__ __forceinline__ float2 rcmc_combine(float x, const float* __restrict__ tab,
+                                               const float2 (&a)[8])
+{
+    const float xf = x * (float)RCMC_INTERVALS;
+    const int b = min((int)xf, RCMC_INTERVALS - 1);
+    const float u = xf - (float)b;
+    const float* p = tab + b;
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const float c0 = p[(t * 4 + 0) * RCMC_INTERVALS];
+        const float c1 = p[(t * 4 + 1) * RCMC_INTERVALS];
+        const float c2 = p[(t * 4 + 2) * RCMC_INTERVALS];
+        const float c3 = p[(t * 4 + 3) * RCMC_INTERVALS];
+        const float w = fmaf(fmaf(fmaf(c3, u, c2), u, c1), u, c0);
+        acc.x = fmaf(w, a[t].x, acc.x);
+        acc.y = fmaf(w, a[t].y, acc.y);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ float2 ld_off(const float2* __restrict__ base, uint32_t byte_off)
+{
+    return *(const float2*)((const char*)base + byte_off);
+}
+
+// RCMC output y[n][k] from range-Doppler A[Nr][Na]:
+//   R0 = r_near + n, s = R0 * stretch_k, i0 = n + floor(s), x = frac(s),
+//   y = sum_t w_t(x) A[i0 + t][k] over t = -3..4 (rows outside [0, Nr) add 0).
+// `interior` promises that every tap row is inside the scene (checked by
+// the caller per line), which removes the per-tap bounds tests.
+__device__ __forceinline__ void rcmc_shift(double R0, int n, double stretch, float& x, int& i0)
+{
+    const double s = R0 * stretch;
+    const double fl = floor(s);
+    x = (float)(s - fl);
+    // shifts beyond +-2^30 cells read nothing but stay defined integers
+    i0 = n + (int)fmax(-1073741824.0, fmin(fl, 1073741824.0));
+}
+
+__device__ __forceinline__ float2 rcmc_gather(const float2* __restrict__ A, int na, int nr, int k,
+                                              float x, int i0, const float* __restrict__ tab,
+                                              bool interior)
+{
+    float2 a[8];
+    if (interior) {
+        const uint32_t step = (uint32_t)na * 8u;
+        uint32_t off = ((uint32_t)(i0 - 3) * (uint32_t)na + (uint32_t)k) * 8u;
+#pragma unroll
+        for (int i = 0; i < 8; ++i, off += step) a[i] = ld_off(A, off);
     } else {
-        const double s = R0 * ra.stretch[k];
-        const double fl = floor(s);
-        const float x = (float)(s - fl);
-        // shifts beyond +-2^30 cells read nothing but stay defined integers
-        const int i0 = n + (int)fmax(-1073741824.0, fmin(fl, 1073741824.0));
-        float2 a[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int r = i0 + i - 3;
-            a[i] = (r >= 0 && r < ra.nr) ? A[(size_t)r * na + k] : make_float2(0.f, 0.f);
+            a[i] = (r >= 0 && r < nr) ? A[(size_t)r * na + k] : make_float2(0.f, 0.f);
         }
-        y = kaiser_sinc8(x, ra.b4, ra.b64, a);
     }
-    if (phase) {
-        const double ph = R0 * ra.rate[k];
-        float f = (float)(ph - floor(ph));
-        if (f > 0.5f) f -= 1.0f;
-        float sn, cs;
-        sincospif(2.0f * f, &sn, &cs);
-        y = c_mul(y, make_float2(cs * scale, sn * scale));
+    return rcmc_combine(x, tab, a);
+}
+
+template <int TAPS>
+__device__ __forceinline__ float2 rcmc_value(const float2* __restrict__ A, int na, int n, int k,
+                                             const RcmcArgs& ra, const float* __restrict__ tab,
+                                             bool interior)
+{
+    if constexpr (TAPS == 0) {
+        return ld_off(A, ((uint32_t)n * (uint32_t)na + (uint32_t)k) * 8u);
+    } else {
+        float x;
+        int i0;
+        rcmc_shift(ra.r_near + (double)n, n, ra.stretch[k], x, i0);
+        return rcmc_gather(A, na, ra.nr, k, x, i0, tab, interior);
     }
-    return y;
+}
+
+// exp(+j 2 pi frac(R0 * rate)) * scale: the phase in turns is reduced in
+// FP64, then the hardware sine/cosine (argument in turns, max abs error
+// 1.3e-7 on [-1/2, 1/2], measured on gfx950) evaluate it.
+__device__ __forceinline__ float2 az_phase_of(double R0, double rate, float scale)
+{
+    const double ph = R0 * rate;
+    float f = (float)(ph - floor(ph));
+    if (f > 0.5f) f -= 1.0f;
+    return make_float2(__builtin_amdgcn_cosf(f) * scale, __builtin_amdgcn_sinf(f) * scale);
+}
+
+__device__ __forceinline__ float2 az_phase(const RcmcArgs& ra, int n, int k, float scale)
+{
+    return az_phase_of(ra.r_near + (double)n, ra.rate[k], scale);
+}
+
+// Every tap row of output line n lies inside [0, Nr).
+__device__ __forceinline__ bool rcmc_interior(const RcmcArgs& ra, int n)
+{
+    const double smax = (ra.r_near + (double)n) * ra.stretch_max;
+    return n >= 3 && (double)n + smax + 6.0 <= (double)(ra.nr - 1);
+}
+
+// Samples y[m] = RCMC(n, k_m) * phase_m for the 16 columns k_m = t + m*T
+// of one thread, all tap rows inside the scene.  The eight gathers of
+// column m+1 are in flight while column m is combined (vector-memory loads
+// complete in order, so the wait for column m leaves m+1's loads pending).
+// The eight tap samples A[i0 - 3 + i][k].  EDGE: rows outside [0, nr) are
+// read at a clamped (valid) row and replaced by zero, without branches.
+template <int N, bool EDGE>
+__device__ __forceinline__ void rcmc_gather8(float2 (&a)[8], const float2* __restrict__ A, int k,
+                                             int i0, int nr)
+{
+    if constexpr (!EDGE) {
+        constexpr uint32_t step = (uint32_t)N * 8u;
+        uint32_t off = ((uint32_t)(i0 - 3) * (uint32_t)N + (uint32_t)k) * 8u;
+#pragma unroll
+        for (int i = 0; i < 8; ++i, off += step) a[i] = ld_off(A, off);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int r = i0 - 3 + i;
+            const int rc = min(max(r, 0), nr - 1);
+            const float2 v = ld_off(A, ((uint32_t)rc * (uint32_t)N + (uint32_t)k) * 8u);
+            const bool in = (r >= 0) & (r < nr);
+            a[i] = make_float2(in ? v.x : 0.f, in ? v.y : 0.f);
+        }
+    }
+}
+
+// Samples y[m] = RCMC(n, k_m) * phase_m for the 16 columns k_m = t + m*T
+// of one thread.  The gathers of column m+1 are in flight while column m is
+// combined (vector-memory loads complete in order, so waiting for column m
+// leaves m+1's loads pending); sched_barrier(0) keeps the scheduler from
+// hoisting every gather to the top, which would need ~256 registers.
+template <int N, bool EDGE>
+__device__ __forceinline__ void rcmc_row(float2 (&x)[line_e(N)], const float2* __restrict__ A, int t,
+                                         int nr, const float (&xs)[line_e(N)], const int (&i0s)[line_e(N)],
+                                         const float2 (&ph)[line_e(N)], const float* __restrict__ tab)
+{
+    constexpr int T = LineGeom<N>::T;
+    constexpr int E = line_e(N);
+    float2 a0[8], a1[8];
+    rcmc_gather8<N, EDGE>(a0, A, t, i0s[0], nr);
+#pragma unroll
+    for (int m = 0; m < E; m += 2) {
+        rcmc_gather8<N, EDGE>(a1, A, t + (m + 1) * T, i0s[m + 1], nr);
+        __builtin_amdgcn_sched_barrier(0);
+        x[m] = c_mul(rcmc_combine(xs[m], tab, a0), ph[m]);
+        __builtin_amdgcn_sched_barrier(0);
+        if (m + 2 < E) rcmc_gather8<N, EDGE>(a0, A, t + (m + 2) * T, i0s[m + 2], nr);
+        __builtin_amdgcn_sched_barrier(0);
+        x[m + 1] = c_mul(rcmc_combine(xs[m + 1], tab, a1), ph[m + 1]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
 }
 
 template <int N, int TAPS>
 __global__ __launch_bounds__(LineLaunch<N>::BLOCK) void
 k_rcmc_az(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
-          const float2* __restrict__ tw)
+               const float2* __restrict__ tw)
 {
     using L = LineLaunch<N>;
+    constexpr int E = line_e(N);
     extern __shared__ float2 smem[];
+    // The weight table and the line buffers share LDS: the table is only read
+    // while the RCMC samples are formed, before the first FFT exchange.
+    float* tab = (float*)smem;
     const int lines = ra.nr;
     const int groups = (lines + L::LPW - 1) / L::LPW;
     const int g = xcd_group(blockIdx.x, groups);
@@ -327,26 +482,57 @@ k_rcmc_az(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
     const int n = g * L::LPW + sub;
     const bool live = n < lines;
     float2* lds = smem + sub * LineGeom<N>::LDS;
-    float2 x[16];
     constexpr float scale = 1.0f / (float)N;
+    const double R0 = ra.r_near + (double)n;
+
+    // per-Doppler-bin quantities first: their loads overlap the table copy
+    float xs[E];
+    int i0s[E];
+    float2 ph[E];
 #pragma unroll
-    for (int m = 0; m < 16; ++m)
-        x[m] = live ? rcmc_sample<TAPS>(A, N, n, t + m * L::T, ra, scale, true)
-                    : make_float2(0.f, 0.f);
+    for (int m = 0; m < E; ++m) {
+        const int k = t + m * L::T;
+        ph[m] = az_phase_of(R0, ra.rate[k], scale);
+        if constexpr (TAPS != 0) rcmc_shift(R0, n, ra.stretch[k], xs[m], i0s[m]);
+    }
+    if constexpr (TAPS != 0) {
+        load_rcmc_table(tab, ra.table, threadIdx.x, L::BLOCK);
+        __syncthreads();
+    }
+    float2 x[E];
+    if (!live) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) x[m] = make_float2(0.f, 0.f);
+    } else if constexpr (TAPS == 0) {
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            x[m] = c_mul(ld_off(A, ((uint32_t)n * (uint32_t)N + (uint32_t)(t + m * L::T)) * 8u), ph[m]);
+    } else if (rcmc_interior(ra, n)) {
+        rcmc_row<N, false>(x, A, t, ra.nr, xs, i0s, ph, tab);
+    } else {
+        rcmc_row<N, true>(x, A, t, ra.nr, xs, i0s, ph, tab);
+    }
+    if constexpr (TAPS != 0) __syncthreads();     // table reads done before LDS reuse
     fft_line<N, true>(x, lds, tw, t);
     if (live) store_line<N>(x, out + (size_t)n * N, t);
 }
 
-// Unfused comparator: RCMC interpolation alone (one sample per thread).
+// Unfused comparator: RCMC interpolation alone (grid-stride, one sample per
+// thread per iteration).
 template <int TAPS>
 __global__ __launch_bounds__(256) void k_rcmc_interp(const float2* __restrict__ A,
                                                      float2* __restrict__ out, int na, RcmcArgs ra)
 {
+    __shared__ float tab[RCMC_TAB];
+    if constexpr (TAPS != 0) {
+        load_rcmc_table(tab, ra.table, threadIdx.x, 256);
+        __syncthreads();
+    }
     const long long total = (long long)ra.nr * na;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
         const int n = (int)(e / na), k = (int)(e % na);
-        out[e] = rcmc_sample<TAPS>(A, na, n, k, ra, 1.0f, false);
+        out[e] = rcmc_value<TAPS>(A, na, n, k, ra, tab, false);
     }
 }
 
@@ -359,16 +545,23 @@ __global__ __launch_bounds__(256) void k_az_phase(const float2* __restrict__ in,
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
         const int n = (int)(e / na), k = (int)(e % na);
-        const double ph = (ra.r_near + (double)n) * ra.rate[k];
-        float f = (float)(ph - floor(ph));
-        if (f > 0.5f) f -= 1.0f;
-        float sn, cs;
-        sincospif(2.0f * f, &sn, &cs);
-        out[e] = c_mul(in[e], make_float2(cs * scale, sn * scale));
+        out[e] = c_mul(in[e], az_phase(ra, n, k, scale));
     }
 }
 
 // ===================================================== launchers
+static RcmcArgs make_rcmc_args(const RcmcHost& rh)
+{
+    RcmcArgs ra{};
+    ra.stretch = rh.stretch;
+    ra.rate = rh.rate;
+    ra.table = rh.table;
+    ra.r_near = rh.r_near;
+    ra.stretch_max = rh.stretch_max;
+    ra.nr = rh.nr;
+    return ra;
+}
+
 static int grid_for(long long work, int per_block)
 {
     long long g = (work + per_block - 1) / per_block;
@@ -380,24 +573,39 @@ template <int N>
 static hipError_t set_lds_limit()
 {
     using L = LineLaunch<N>;
+    constexpr int rcmc_bytes = L::LDS_BYTES;
     hipError_t e = hipSuccess;
     if (L::LDS_BYTES > 64 * 1024) {
-        e = hipFuncSetAttribute((const void*)k_line_fused<N>,
+        e = hipFuncSetAttribute((const void*)k_line<N, LK_FUSED>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, L::LDS_BYTES);
         if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_line_fft<N, false>,
+            e = hipFuncSetAttribute((const void*)k_line<N, LK_FWD>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, L::LDS_BYTES);
         if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_line_fft<N, true>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, L::LDS_BYTES);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_rcmc_az<N, 0>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, L::LDS_BYTES);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_rcmc_az<N, 8>,
+            e = hipFuncSetAttribute((const void*)k_line<N, LK_INV>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, L::LDS_BYTES);
     }
+    if (e == hipSuccess && rcmc_bytes > 64 * 1024) {
+        e = hipFuncSetAttribute((const void*)k_rcmc_az<N, 0>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, rcmc_bytes);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_rcmc_az<N, 8>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, rcmc_bytes);
+    }
     return e;
+}
+
+template <int N, int KIND>
+static hipError_t launch_k_line(const float2* in, float2* out, int lines, const float2* H,
+                                const float2* tw, float scale, hipStream_t s)
+{
+    using L = LineLaunch<N>;
+    const int groups = (lines + L::LPW - 1) / L::LPW;
+    if (groups == 0) return hipSuccess;
+    const int grid = groups;
+    hipLaunchKernelGGL((k_line<N, KIND>), dim3(grid), dim3(L::BLOCK), L::LDS_BYTES, s, in, out,
+                       lines, H, tw, scale);
+    return hipGetLastError();
 }
 
 template <int N>
@@ -408,29 +616,24 @@ static hipError_t launch_line_n(LineOp op, const float2* in, float2* out, int li
     using L = LineLaunch<N>;
     static const hipError_t attr = set_lds_limit<N>();
     if (attr != hipSuccess) return attr;
-    const int groups = (lines + L::LPW - 1) / L::LPW;
-    if (groups == 0) return hipSuccess;
-    dim3 grid(groups), block(L::BLOCK);
     switch (op) {
-    case LineOp::Fused:
-        hipLaunchKernelGGL(k_line_fused<N>, grid, block, L::LDS_BYTES, s, in, out, lines, H, tw);
-        break;
-    case LineOp::Forward:
-        hipLaunchKernelGGL((k_line_fft<N, false>), grid, block, L::LDS_BYTES, s, in, out, lines, tw,
-                           scale);
-        break;
-    case LineOp::Inverse:
-        hipLaunchKernelGGL((k_line_fft<N, true>), grid, block, L::LDS_BYTES, s, in, out, lines, tw,
-                           scale);
-        break;
-    case LineOp::RcmcAz:
+    case LineOp::Fused: return launch_k_line<N, LK_FUSED>(in, out, lines, H, tw, 1.0f, s);
+    case LineOp::Forward: return launch_k_line<N, LK_FWD>(in, out, lines, nullptr, tw, scale, s);
+    case LineOp::Inverse: return launch_k_line<N, LK_INV>(in, out, lines, nullptr, tw, scale, s);
+    case LineOp::RcmcAz: {
+        const int groups = (lines + L::LPW - 1) / L::LPW;
+        if (groups == 0) return hipSuccess;
+        static_assert(L::LDS_BYTES >= RCMC_TAB * (int)sizeof(float), "table fits the line LDS");
         if (taps == 8)
-            hipLaunchKernelGGL((k_rcmc_az<N, 8>), grid, block, L::LDS_BYTES, s, in, out, *ra, tw);
+            hipLaunchKernelGGL((k_rcmc_az<N, 8>), dim3(groups), dim3(L::BLOCK), L::LDS_BYTES, s, in,
+                               out, *ra, tw);
         else
-            hipLaunchKernelGGL((k_rcmc_az<N, 0>), grid, block, L::LDS_BYTES, s, in, out, *ra, tw);
-        break;
+            hipLaunchKernelGGL((k_rcmc_az<N, 0>), dim3(groups), dim3(L::BLOCK), L::LDS_BYTES, s, in,
+                               out, *ra, tw);
+        return hipGetLastError();
     }
-    return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_line(LineOp op, int n, const void* in, void* out, int lines, const void* H,
@@ -439,12 +642,7 @@ hipError_t launch_line(LineOp op, int n, const void* in, void* out, int lines, c
     RcmcArgs ra{};
     int taps = 0;
     if (rh) {
-        ra.stretch = rh->stretch;
-        ra.rate = rh->rate;
-        ra.r_near = rh->r_near;
-        ra.b4 = (float)(rh->beta * rh->beta / 4.0);
-        ra.b64 = (float)(rh->beta * rh->beta / 64.0);
-        ra.nr = rh->nr;
+        ra = make_rcmc_args(*rh);
         taps = rh->taps;
     }
     auto i = (const float2*)in;
@@ -500,8 +698,7 @@ hipError_t launch_corner_turn(const void* in, void* out, int rows, int cols, hip
 
 hipError_t launch_rcmc_interp(const void* A, void* out, int na, const RcmcHost& rh, hipStream_t s)
 {
-    RcmcArgs ra{rh.stretch, rh.rate, rh.r_near, (float)(rh.beta * rh.beta / 4.0),
-                (float)(rh.beta * rh.beta / 64.0), rh.nr};
+    const RcmcArgs ra = make_rcmc_args(rh);
     const long long total = (long long)rh.nr * na;
     if (rh.taps == 8)
         hipLaunchKernelGGL(k_rcmc_interp<8>, dim3(grid_for(total, 256)), dim3(256), 0, s,
@@ -515,7 +712,7 @@ hipError_t launch_rcmc_interp(const void* A, void* out, int na, const RcmcHost& 
 hipError_t launch_az_phase(const void* in, void* out, int na, const RcmcHost& rh, float scale,
                            hipStream_t s)
 {
-    RcmcArgs ra{rh.stretch, rh.rate, rh.r_near, 0.f, 0.f, rh.nr};
+    const RcmcArgs ra = make_rcmc_args(rh);
     const long long total = (long long)rh.nr * na;
     hipLaunchKernelGGL(k_az_phase, dim3(grid_for(total, 256)), dim3(256), 0, s, (const float2*)in,
                        (float2*)out, na, ra, scale);
@@ -526,7 +723,8 @@ hipError_t launch_gen_twiddles(void* tw, int n, hipStream_t s)
 {
     const int cnt = twiddle_table_size(n);
     if (cnt <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gen_twiddles, dim3((cnt + 255) / 256), dim3(256), 0, s, (float2*)tw, n);
+    hipLaunchKernelGGL(k_gen_twiddles, dim3((cnt + 255) / 256), dim3(256), 0, s, (float2*)tw, n,
+                       line_e(n));
     return hipGetLastError();
 }
 
@@ -537,6 +735,14 @@ hipError_t launch_gen_chirp_filter(void* H, int n, int len, double K, int sign, 
                        len, K, sign, scale);
     return hipGetLastError();
 }
+
+hipError_t launch_gen_rcmc_table(float* tab, double beta, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gen_rcmc_table, dim3(1), dim3(RCMC_INTERVALS), 0, s, tab, beta);
+    return hipGetLastError();
+}
+
+int rcmc_table_floats() { return RCMC_TAB; }
 
 hipError_t launch_gen_hyper_tables(double* stretch, double* rate, int na, double lam, double v,
                                    hipStream_t s)

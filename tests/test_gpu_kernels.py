@@ -71,6 +71,22 @@ def test_tables_match_oracle(plans):
     assert np.max(np.abs(rt / (2.0 * D / c2["lam"]) - 1.0)) < 1e-15
 
 
+def test_rcmc_weight_table_matches_oracle(plans):
+    """The plan's piecewise-cubic weights reproduce the exact Kaiser-sinc
+    weights of the oracle to < 1e-7 everywhere on [0, 1)."""
+    p = plans(config("c2"))
+    tab = sar.sar_plan_get_table(p.handle, 4).astype(np.float64)
+    nb = sar._lib.RCMC_INTERVALS
+    c = tab.reshape(8, 4, nb)
+    worst = 0.0
+    for x in np.concatenate([np.linspace(0, 1, 4001, endpoint=False), [1 - 1e-9, 0.5, 1e-7]]):
+        b = min(int(x * nb), nb - 1)
+        u = x * nb - b
+        w = c[:, 0, b] + u * (c[:, 1, b] + u * (c[:, 2, b] + u * c[:, 3, b]))
+        worst = max(worst, float(np.max(np.abs(w - O.rcmc_weights(x, 2.5, 8)))))
+    assert worst < 1e-7, worst
+
+
 @pytest.mark.parametrize("n", SIZES)
 @pytest.mark.parametrize("inverse", [0, 1])
 def test_line_fft(n, inverse, plans):
