@@ -9,9 +9,10 @@ range migration, 8-tap Kaiser-sinc RCMC, 5 point targets, 20 dB noise),
 with the raw scene resident in HBM.  Prints one JSON line.
 
 Alongside the headline it times, with HIP events on the stream the kernels
-run on: each kernel of the fused pipeline alone (the slowest one carries the
-roofline figure), the unfused 3-dispatch comparator, and the FP64 CPU oracle
-on the host cores (cpu_baseline).
+run on: each kernel of the fused pipeline inside the pipeline (events between
+the four launches of a step; the slowest kernel carries the roofline figure),
+the unfused 3-dispatch comparator, and the FP64 CPU oracle on the host cores
+(cpu_baseline).
 """
 from __future__ import annotations
 
@@ -90,15 +91,29 @@ def main():
     ms_per_step = wall / args.steps * 1e3
     value = px / (ms_per_step * 1e-3) / 1e6
 
-    # ---- per-kernel launch durations (same stream, HIP events) ----
-    A = work
-    B = img
-    kern = {}
+    # ---- per-kernel durations inside the pipeline (same stream, HIP events
+    # between the four launches of each step: the kernels of sar_rda_execute
+    # in the same order, on the same buffers) ----
+    A, B = work, img
+    names = ["range_fused", "corner_turn", "azimuth_fft", "rcmc_azimuth"]
+    calls = [lambda: sar.sar_range_compress(h, raw, A, stream),
+             lambda: sar.sar_corner_turn(h, A, B, Na, Nr, stream),
+             lambda: sar.sar_azimuth_fft(h, B, A, stream),
+             lambda: sar.sar_rcmc_azimuth(h, A, B, stream)]
     reps = args.kernel_reps
-    kern["range_fused"], _ = timed(lambda: sar.sar_range_compress(h, raw, A, stream), reps, 2)
-    kern["corner_turn"], _ = timed(lambda: sar.sar_corner_turn(h, A, B, Na, Nr, stream), reps, 2)
-    kern["azimuth_fft"], _ = timed(lambda: sar.sar_azimuth_fft(h, B, A, stream), reps, 2)
-    kern["rcmc_azimuth"], _ = timed(lambda: sar.sar_rcmc_azimuth(h, A, B, stream), reps, 2)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(reps)]
+    for _ in range(2):
+        for c in calls:
+            c()
+    torch.cuda.synchronize()
+    for r in range(reps):
+        ev[r][0].record(stream)
+        for i, c in enumerate(calls):
+            c()
+            ev[r][i + 1].record(stream)
+    torch.cuda.synchronize()
+    kern = {n: sum(ev[r][i].elapsed_time(ev[r][i + 1]) for r in range(reps)) / reps
+            for i, n in enumerate(names)}
     dom = max(kern, key=kern.get)
     dom_bytes = KERNEL_BYTES_PER_PX[dom] * px
     achieved = dom_bytes / (kern[dom] * 1e-3) / 1e9

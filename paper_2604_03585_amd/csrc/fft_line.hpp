@@ -200,15 +200,15 @@ template <int N, int P> struct PassTw {
     float2 w[COUNT];
 };
 
-template <int N, int P>
+template <int N, int P, bool TWP>
 __device__ __forceinline__ void load_tw(PassTw<N, P>& pt, const float2* __restrict__ tw, int t)
 {
     using G = LineGeom<N>;
-    if constexpr (PassTw<N, P>::ANY && G::radix(P) == 16) {
-        // Radix-16 pass: W^1 and W^4 come from the table, the other powers are
-        // products (at most four roundings deep, ~3e-7 relative).  Thirteen
-        // complex products replace thirteen table reads: the fused kernel is
-        // bound by vector-memory issue, not by VALU.
+    if constexpr (TWP && PassTw<N, P>::ANY && G::radix(P) == 16) {
+        // TWP, radix-16 pass: W^1 and W^4 come from the table, the other
+        // powers are products (at most four roundings deep, ~3e-7 relative).
+        // Thirteen complex products replace thirteen table reads, for kernels
+        // bound by vector-memory issue rather than by VALU.
         constexpr int NS = G::span(P), B = line_e(N) / 16, OFF = G::tw_off(P);
 #pragma unroll
         for (int q = 0; q < B; ++q) {
@@ -288,24 +288,25 @@ struct NoOp {
     __device__ __forceinline__ void operator()() const {}
 };
 
-template <int N, bool INV, int P, class F>
+template <int N, bool INV, bool TWP, int P, class F>
 __device__ __forceinline__ void fft_from(float2 (&x)[line_e(N)], float2* __restrict__ lds,
                                          const float2* __restrict__ tw, int t, F&& before_last)
 {
     if constexpr (P < LineGeom<N>::NP) {
         if constexpr (P == LineGeom<N>::NP - 1) before_last();
         PassTw<N, P> cur;
-        load_tw<N, P>(cur, tw, t);
+        load_tw<N, P, TWP>(cur, tw, t);
         fft_pass<N, P, INV>(x, lds, cur, t);
-        fft_from<N, INV, P + 1>(x, lds, tw, t, before_last);
+        fft_from<N, INV, TWP, P + 1>(x, lds, tw, t, before_last);
     }
 }
 
-template <int N, bool INV, class F = NoOp>
+// TWP selects twiddles by products (fewer loads, more VALU) or table reads.
+template <int N, bool INV, bool TWP = true, class F = NoOp>
 __device__ __forceinline__ void fft_line(float2 (&x)[line_e(N)], float2* __restrict__ lds,
                                          const float2* __restrict__ tw, int t, F&& before_last = F())
 {
-    fft_from<N, INV, 0>(x, lds, tw, t, before_last);
+    fft_from<N, INV, TWP, 0>(x, lds, tw, t, before_last);
 }
 
 }  // namespace sar

@@ -158,8 +158,17 @@ sar_status check_ptr(const void* p, const char* name)
 
 sar::RcmcHost rcmc_host(const sar_plan_s* P)
 {
-    return sar::RcmcHost{P->stretch, P->rate, P->rcmc_tab, P->p.r_near,
-                         P->stretch_max, P->p.rcmc_taps, P->p.Nr};
+    sar::RcmcHost h{};
+    h.stretch = P->stretch;
+    h.rate = P->rate;
+    h.table = P->rcmc_tab;
+    h.r_near = P->p.r_near;
+    h.stretch_max = P->stretch_max;
+    h.x_per_bin = P->p.lambda / (2.0 * P->p.v * (double)P->p.Na);
+    h.two_over_lam = 2.0 / P->p.lambda;
+    h.taps = P->p.rcmc_taps;
+    h.nr = P->p.Nr;
+    return h;
 }
 
 using sar::LineOp;

@@ -23,6 +23,8 @@ struct RcmcHost {
     const float* table;      // device, rcmc_table_floats() weight coefficients
     double r_near;
     double stretch_max;      // largest stretch_k (at |f| = 1/2)
+    double x_per_bin;        // lambda / (2 v Na)
+    double two_over_lam;     // 2 / lambda
     int taps;                // 0 or 8
     int nr;                  // range lines (rows of the [Nr][Na] data)
 };

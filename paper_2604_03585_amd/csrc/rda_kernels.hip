@@ -302,8 +302,24 @@ struct RcmcArgs {
     const float* table;      // RCMC_TAB weight coefficients (global)
     double r_near;
     double stretch_max;      // max_k stretch_k (|f| = 1/2)
+    double x_per_bin;        // lambda / (2 v Na): x_k = signed bin * x_per_bin
+    double two_over_lam;     // 2 / lambda
     int nr;
 };
+
+// The per-bin geometry computed from the bin index, exactly as the plan's
+// tables are built: f_k in fftfreq order, x = lambda f / (2 v),
+// D = sqrt(1 - x^2), stretch = x^2 / (D (1 + D)), rate = 2 D / lambda.
+__device__ __forceinline__ void bin_geometry(const RcmcArgs& ra, int k, int na, double& stretch,
+                                             double& rate)
+{
+    const int kk = k < na / 2 ? k : k - na;
+    const double x = (double)kk * ra.x_per_bin;
+    const double x2 = x * x;
+    const double D = sqrt(1.0 - x2);
+    stretch = x2 / (D * (1.0 + D));
+    rate = D * ra.two_over_lam;
+}
 
 __device__ __forceinline__ void load_rcmc_table(float* __restrict__ lds_tab,
                                                 const float* __restrict__ tab, int tid, int nthreads)
@@ -517,6 +533,136 @@ k_rcmc_az(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
     if (live) store_line<N>(x, out + (size_t)n * N, t);
 }
 
+// Two output rows n, n+1 per line slot.  For each column their 8-tap
+// windows start at i0(n) - 3 and i0(n+1) - 3 with i0(n+1) - i0(n) = 1 + d,
+// d in {0, 1} (requires stretch < 1), so ten rows i0(n) - 3 .. i0(n) + 6
+// cover both: 10 gathers for 2 samples instead of 16.  The per-bin
+// geometry is computed, not loaded, so the gathers of the next column can be
+// issued before the current column is combined without a load-to-load chain.
+template <int N, bool EDGE>
+__device__ __forceinline__ void rcmc_gather10(float2 (&w)[10], const float2* __restrict__ A,
+                                              int k, int i0, int nr)
+{
+    if constexpr (!EDGE) {
+        constexpr uint32_t step = (uint32_t)N * 8u;
+        uint32_t off = ((uint32_t)(i0 - 3) * (uint32_t)N + (uint32_t)k) * 8u;
+#pragma unroll
+        for (int i = 0; i < 10; ++i, off += step) w[i] = ld_off(A, off);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 10; ++i) {
+            const int r = i0 - 3 + i;
+            const int rc = min(max(r, 0), nr - 1);
+            const float2 v = ld_off(A, ((uint32_t)rc * (uint32_t)N + (uint32_t)k) * 8u);
+            const bool in = (r >= 0) & (r < nr);
+            w[i] = make_float2(in ? v.x : 0.f, in ? v.y : 0.f);
+        }
+    }
+}
+
+struct ColPair {
+    float xa, xb;        // fractional positions for rows n, n+1
+    int i0;              // i0(n)
+    bool d;              // i0(n+1) - i0(n) == 2
+    float2 pa, pb;       // azimuth phases (with 1/Na) for rows n, n+1
+};
+
+__device__ __forceinline__ ColPair col_pair(const RcmcArgs& ra, int n, int k, int na, float scale)
+{
+    double stretch, rate;
+    bin_geometry(ra, k, na, stretch, rate);
+    const double R0 = ra.r_near + (double)n;
+    ColPair c;
+    int ib;
+    rcmc_shift(R0, n, stretch, c.xa, c.i0);
+    rcmc_shift(R0 + 1.0, n + 1, stretch, c.xb, ib);
+    c.d = (ib - c.i0) == 2;
+    c.pa = az_phase_of(R0, rate, scale);
+    c.pb = az_phase_of(R0 + 1.0, rate, scale);
+    return c;
+}
+
+template <int N, bool EDGE>
+__device__ __forceinline__ void rcmc_pair_combine(float2& ya, float2& yb, const ColPair& c,
+                                                  const float2 (&w)[10],
+                                                  const float* __restrict__ tab)
+{
+    float2 ta[8], tb[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        ta[i] = w[i];
+        tb[i] = c.d ? w[i + 2] : w[i + 1];
+    }
+    ya = c_mul(rcmc_combine(c.xa, tab, ta), c.pa);
+    yb = c_mul(rcmc_combine(c.xb, tab, tb), c.pb);
+}
+
+template <int N, bool EDGE>
+__device__ __forceinline__ void rcmc_rows2(float2 (&xa)[line_e(N)], float2 (&xb)[line_e(N)],
+                                           const float2* __restrict__ A, const RcmcArgs& ra,
+                                           int n, int t, const float* __restrict__ tab)
+{
+    constexpr int T = LineGeom<N>::T;
+    constexpr int E = line_e(N);
+    constexpr float scale = 1.0f / (float)N;
+    // two named buffers, alternated by column parity (no register copies)
+    ColPair c0 = col_pair(ra, n, t, N, scale), c1;
+    float2 w0[10], w1[10];
+    rcmc_gather10<N, EDGE>(w0, A, t, c0.i0, ra.nr);
+#pragma unroll
+    for (int m = 0; m < E; m += 2) {
+        c1 = col_pair(ra, n, t + (m + 1) * T, N, scale);
+        rcmc_gather10<N, EDGE>(w1, A, t + (m + 1) * T, c1.i0, ra.nr);
+        __builtin_amdgcn_sched_barrier(0);
+        rcmc_pair_combine<N, EDGE>(xa[m], xb[m], c0, w0, tab);
+        __builtin_amdgcn_sched_barrier(0);
+        if (m + 2 < E) {
+            c0 = col_pair(ra, n, t + (m + 2) * T, N, scale);
+            rcmc_gather10<N, EDGE>(w0, A, t + (m + 2) * T, c0.i0, ra.nr);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        rcmc_pair_combine<N, EDGE>(xa[m + 1], xb[m + 1], c1, w1, tab);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(LineLaunch<N>::BLOCK) void
+k_rcmc_az2(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
+           const float2* __restrict__ tw)
+{
+    using L = LineLaunch<N>;
+    constexpr int E = line_e(N);
+    extern __shared__ float2 smem[];
+    float* tab = (float*)smem;                    // shares LDS with the line buffers
+    const int pairs = ra.nr / 2;
+    const int groups = (pairs + L::LPW - 1) / L::LPW;
+    const int g = xcd_group(blockIdx.x, groups);
+    const int sub = threadIdx.x / L::T, t = threadIdx.x % L::T;
+    const int pr = g * L::LPW + sub;
+    const bool live = pr < pairs;
+    const int n = 2 * pr;
+    float2* lds = smem + sub * LineGeom<N>::LDS;
+    load_rcmc_table(tab, ra.table, threadIdx.x, L::BLOCK);
+    __syncthreads();
+    float2 xa[E], xb[E];
+    if (!live) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) xa[m] = xb[m] = make_float2(0.f, 0.f);
+    } else {
+        const double smax = (ra.r_near + (double)n + 1.0) * ra.stretch_max;
+        if (n >= 3 && (double)n + 1.0 + smax + 6.0 <= (double)(ra.nr - 1))
+            rcmc_rows2<N, false>(xa, xb, A, ra, n, t, tab);
+        else
+            rcmc_rows2<N, true>(xa, xb, A, ra, n, t, tab);
+    }
+    __syncthreads();                              // table reads done before LDS reuse
+    fft_line<N, true>(xa, lds, tw, t);
+    if (live) store_line<N>(xa, out + (size_t)n * N, t);
+    fft_line<N, true>(xb, lds, tw, t);
+    if (live) store_line<N>(xb, out + (size_t)(n + 1) * N, t);
+}
+
 // Unfused comparator: RCMC interpolation alone (grid-stride, one sample per
 // thread per iteration).
 template <int TAPS>
@@ -558,6 +704,8 @@ static RcmcArgs make_rcmc_args(const RcmcHost& rh)
     ra.table = rh.table;
     ra.r_near = rh.r_near;
     ra.stretch_max = rh.stretch_max;
+    ra.x_per_bin = rh.x_per_bin;
+    ra.two_over_lam = rh.two_over_lam;
     ra.nr = rh.nr;
     return ra;
 }
@@ -590,6 +738,9 @@ static hipError_t set_lds_limit()
                                 hipFuncAttributeMaxDynamicSharedMemorySize, rcmc_bytes);
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_rcmc_az<N, 8>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, rcmc_bytes);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_rcmc_az2<N>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, rcmc_bytes);
     }
     return e;
@@ -624,7 +775,11 @@ static hipError_t launch_line_n(LineOp op, const float2* in, float2* out, int li
         const int groups = (lines + L::LPW - 1) / L::LPW;
         if (groups == 0) return hipSuccess;
         static_assert(L::LDS_BYTES >= RCMC_TAB * (int)sizeof(float), "table fits the line LDS");
-        if (taps == 8)
+        if (taps == 8 && ra->stretch_max < 0.5 && (lines & 1) == 0) {
+            const int g2 = (lines / 2 + L::LPW - 1) / L::LPW;
+            hipLaunchKernelGGL((k_rcmc_az2<N>), dim3(g2), dim3(L::BLOCK), L::LDS_BYTES, s, in, out,
+                               *ra, tw);
+        } else if (taps == 8)
             hipLaunchKernelGGL((k_rcmc_az<N, 8>), dim3(groups), dim3(L::BLOCK), L::LDS_BYTES, s, in,
                                out, *ra, tw);
         else
