@@ -1,0 +1,217 @@
+// mfma_fft.hpp -- split-precision radix-16 butterflies on gfx950 MFMA.
+//
+// The precision variant computes every radix-16 DFT of a Stockham pass as a
+// small dense matrix product (the paper's DFT_8 as four real MMAs, Sec. III.A
+// eqs. 1-2, widened to radix 16 and to the 16x16x32 MFMA shape):
+//
+//     [Yr]   [Fr  -Fi] [Xr]          F[k][n] = exp(-+2 pi i k n / 16) / 16
+//     [Yi] = [Fi   Fr] [Xi] ,        (32 x 32 real, applied to 16 DFTs at once)
+//
+// with v_mfma_f32_16x16x32_{f16,bf16}: D(16x16) = A(16x32) B(32x16), where a
+// wave's lane l holds A[l%16][8(l/16)+i], B[8(l/16)+i][l%16] (i < 8) and
+// D[4(l/16)+i][l%16] (i < 4) -- the layout was checked on the device.  The
+// first MFMA of each half gives Yr (A = [Fr -Fi]), the second Yi
+// (A = [Fi Fr]); B is [Xr; Xi] for 16 butterflies.
+//
+// Each FP32 operand is split as x = hi + lo (hi = round(x), lo =
+// round(x - hi)) and the product is accumulated in FP32 as
+// F_hi X_hi + F_hi X_lo + F_lo X_hi (the lo*lo term is dropped).  F carries a
+// factor 1/16 (exact) so that FP16 never overflows: values shrink by at most
+// the DFT's gain; the caller restores 16^passes at the end.  Twiddles are
+// applied in FP32 between passes, on the output side of a pass (where a lane
+// holds complete complex values), already for the next pass.
+//
+// LDS holds the WG's lines in split form: re[] then im[], one pad slot per 16
+// entries, the same bytes as the float2 layout of the FP32 path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft_line.hpp"
+
+namespace sar {
+
+enum Prec { PREC_FP32 = 0, PREC_F16 = 1, PREC_BF16 = 2 };
+
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 b8_t __attribute__((ext_vector_type(8)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <int PREC> struct MfmaT;
+template <> struct MfmaT<PREC_F16> {
+    using scalar = _Float16;
+    using vec = h8_t;
+    __device__ __forceinline__ static f4_t mma(vec a, vec b, f4_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct MfmaT<PREC_BF16> {
+    using scalar = __bf16;
+    using vec = b8_t;
+    __device__ __forceinline__ static f4_t mma(vec a, vec b, f4_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+// hi + lo split of eight FP32 values.
+template <int PREC>
+__device__ __forceinline__ void split8(const float (&v)[8], typename MfmaT<PREC>::vec& hi,
+                                       typename MfmaT<PREC>::vec& lo)
+{
+    using S = typename MfmaT<PREC>::scalar;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const S h = (S)v[i];
+        hi[i] = h;
+        lo[i] = (S)(v[i] - (float)h);
+    }
+}
+
+// The constant DFT operands of one wave: A_r = [Fr -Fi], A_i = [Fi Fr] (x 1/16),
+// each split in hi/lo, in the MFMA A layout for this lane.
+template <int PREC> struct DftOperands {
+    typename MfmaT<PREC>::vec rh, rl, ih, il;
+};
+
+template <int PREC, bool INV>
+__device__ __forceinline__ DftOperands<PREC> dft16_operands(int lane)
+{
+    // cos / sin of 2 pi m / 16, m = 0..15
+    constexpr float C[16] = {1.0f, 0.92387953251128675613f, 0.70710678118654752440f,
+                             0.38268343236508977173f, 0.0f, -0.38268343236508977173f,
+                             -0.70710678118654752440f, -0.92387953251128675613f, -1.0f,
+                             -0.92387953251128675613f, -0.70710678118654752440f,
+                             -0.38268343236508977173f, 0.0f, 0.38268343236508977173f,
+                             0.70710678118654752440f, 0.92387953251128675613f};
+    const int k = lane & 15, q = lane >> 4;
+    float ar[8], ai[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int n = 8 * (q & 1) + i;
+        const int m = (k * n) & 15;
+        const float fr = C[m] * 0.0625f;
+        const float s = C[(m + 12) & 15] * 0.0625f;    // sin(2 pi m/16) = cos(2 pi (m - 4)/16)
+        const float fi = INV ? s : -s;                  // F = exp(-+ i 2 pi m / 16)
+        ar[i] = (q < 2) ? fr : -fi;                     // [Fr -Fi]
+        ai[i] = (q < 2) ? fi : fr;                      // [Fi  Fr]
+    }
+    DftOperands<PREC> d;
+    split8<PREC>(ar, d.rh, d.rl);
+    split8<PREC>(ai, d.ih, d.il);
+    return d;
+}
+
+__device__ __forceinline__ int mf_pad(int i) { return i + (i >> 4); }
+
+// All radix-16 passes of the lines of one workgroup on MFMA, followed by the
+// trailing smaller pass (if any) in FP32.  On entry each thread holds its
+// line's x in the strided register layout (see fft_line.hpp); on exit it
+// holds the transform (scaled back to the plain unnormalised DFT).
+//   lds:   the workgroup's LDS (LPW lines, 2*(N + N/16) floats each)
+//   sub:   this thread's line within the workgroup, t its index in the line
+template <int N, bool INV, int PREC, int LPW, int BLOCK>
+__device__ __forceinline__ void fft_line_mfma(float2 (&x)[16], float* __restrict__ lds,
+                                              const float2* __restrict__ tw, int sub, int t)
+{
+    using G = LineGeom<N, 16>;
+    static_assert(line_e(N) == 16, "the MFMA path uses 16 points per thread");
+    constexpr int T = G::T;
+    constexpr int LL = G::LDS;                   // floats per component per line
+    constexpr int NB = N / 16;                   // butterflies per line and pass
+    constexpr int NMF = G::NFULL;                // radix-16 (MFMA) passes
+    constexpr int GROUPS = LPW * NB / 16;        // 16-butterfly groups per workgroup
+    constexpr int WAVES = BLOCK / 64;
+    constexpr int GPW = GROUPS / WAVES;          // groups per wave
+    static_assert(GROUPS % WAVES == 0 && GPW >= 1, "group split");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float* re = lds;
+    float* im = lds + LPW * LL;
+
+    // registers -> LDS (split)
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int e = sub * LL + mf_pad(t + m * T);
+        re[e] = x[m].x;
+        im[e] = x[m].y;
+    }
+    __syncthreads();
+
+    const DftOperands<PREC> F = dft16_operands<PREC, INV>(lane);
+    const int c = lane & 15, q = lane >> 4;
+
+#pragma unroll
+    for (int p = 0; p < NMF; ++p) {
+        const int NS = p == 0 ? 1 : (p == 1 ? 16 : (p == 2 ? 256 : 4096));
+        const bool next_mfma = (p + 1 < NMF);
+        const int NS2 = NS * 16;                 // span of the next pass
+        const int off2 = next_mfma ? G::tw_off(p + 1) : 0;
+        float2 y[GPW][4];
+#pragma unroll
+        for (int gi = 0; gi < GPW; ++gi) {
+            const int b = (wave * GPW + gi) * 16 + c;          // butterfly in the WG
+            const int s = b / NB, j = b % NB;
+            const float* src = (q < 2 ? re : im) + s * LL;
+            float v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = src[mf_pad(j + (8 * (q & 1) + i) * NB)];
+            typename MfmaT<PREC>::vec bh, bl;
+            split8<PREC>(v, bh, bl);
+            f4_t ar = {0.f, 0.f, 0.f, 0.f}, ai = {0.f, 0.f, 0.f, 0.f};
+            ar = MfmaT<PREC>::mma(F.rh, bh, ar);
+            ar = MfmaT<PREC>::mma(F.rh, bl, ar);
+            ar = MfmaT<PREC>::mma(F.rl, bh, ar);
+            ai = MfmaT<PREC>::mma(F.ih, bh, ai);
+            ai = MfmaT<PREC>::mma(F.ih, bl, ai);
+            ai = MfmaT<PREC>::mma(F.il, bh, ai);
+            const int jm = j & (NS - 1), base = (j / NS) * NS * 16 + jm;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float2 o = make_float2(ar[i], ai[i]);
+                if (next_mfma) {
+                    // pre-twiddle for the next radix-16 pass
+                    const int e = base + (4 * q + i) * NS;
+                    const int j2 = e % NB, i2 = e / NB;
+                    if (i2 > 0) {
+                        float2 w = tw[off2 + (i2 - 1) * NS2 + (j2 & (NS2 - 1))];
+                        if (INV) w.y = -w.y;
+                        o = c_mul(o, w);
+                    }
+                }
+                y[gi][i] = o;
+            }
+        }
+        __syncthreads();                          // every read of this pass is done
+#pragma unroll
+        for (int gi = 0; gi < GPW; ++gi) {
+            const int b = (wave * GPW + gi) * 16 + c;
+            const int s = b / NB, j = b % NB;
+            const int base = (j / NS) * NS * 16 + (j & (NS - 1));
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int e = s * LL + mf_pad(base + (4 * q + i) * NS);
+                re[e] = y[gi][i].x;
+                im[e] = y[gi][i].y;
+            }
+        }
+        __syncthreads();
+    }
+
+    // LDS -> registers, undo the 1/16 per MFMA pass
+    constexpr float undo = (float)(1 << (4 * NMF));
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int e = sub * LL + mf_pad(t + m * T);
+        x[m] = make_float2(re[e] * undo, im[e] * undo);
+    }
+    __syncthreads();                              // LDS free for the caller's next use
+    if constexpr (G::NP > NMF) {
+        // trailing radix-2/4/8 pass in FP32 (its twiddles applied on input)
+        PassTw<N, G::NP - 1> pt;
+        load_tw<N, G::NP - 1, false>(pt, tw, t);
+        fft_pass<N, G::NP - 1, INV>(x, (float2*)nullptr, pt, t);
+    }
+}
+
+}  // namespace sar

@@ -132,8 +132,6 @@ sar_status validate_params(const sar_params* p)
         return fail(SAR_ERR_BAD_PARAM, "schedule=%d unknown", p->schedule);
     if (p->transpose_back != 0 && p->transpose_back != 1)
         return fail(SAR_ERR_BAD_PARAM, "transpose_back must be 0 or 1");
-    if (p->precision != SAR_FP32)
-        return fail(SAR_ERR_UNSUPPORTED, "split-precision butterflies are not built in this library");
     return SAR_OK;
 }
 
@@ -178,13 +176,13 @@ sar_status step_range(const sar_plan_s* P, const void* in, void* out, hipStream_
 {
     const int Nr = P->p.Nr, Na = P->p.Na;
     if (P->p.schedule == SAR_FUSED) {
-        HIP_TRY(sar::launch_line(LineOp::Fused, Nr, in, out, Na, P->Hr, P->tw_r, 1.f, nullptr, s),
+        HIP_TRY(sar::launch_line(LineOp::Fused, Nr, in, out, Na, P->Hr, P->tw_r, 1.f, nullptr, P->p.precision, s),
                 "range fused launch");
     } else {
-        HIP_TRY(sar::launch_line(LineOp::Forward, Nr, in, out, Na, nullptr, P->tw_r, 1.f, nullptr, s),
+        HIP_TRY(sar::launch_line(LineOp::Forward, Nr, in, out, Na, nullptr, P->tw_r, 1.f, nullptr, P->p.precision, s),
                 "range FFT launch");
         HIP_TRY(sar::launch_rowmul(out, out, Na, Nr, P->Hr, s), "range multiply launch");
-        HIP_TRY(sar::launch_line(LineOp::Inverse, Nr, out, out, Na, nullptr, P->tw_r, 1.f, nullptr, s),
+        HIP_TRY(sar::launch_line(LineOp::Inverse, Nr, out, out, Na, nullptr, P->tw_r, 1.f, nullptr, P->p.precision, s),
                 "range IFFT launch");
     }
     return SAR_OK;
@@ -202,27 +200,27 @@ sar_status step_azimuth(const sar_plan_s* P, const void* in, void* out, void* wo
     const int Nr = P->p.Nr, Na = P->p.Na;
     if (P->p.az_model == SAR_AZ_LFM) {
         if (P->p.schedule == SAR_FUSED) {
-            HIP_TRY(sar::launch_line(LineOp::Fused, Na, in, out, Nr, P->Ha, P->tw_a, 1.f, nullptr, s),
+            HIP_TRY(sar::launch_line(LineOp::Fused, Na, in, out, Nr, P->Ha, P->tw_a, 1.f, nullptr, P->p.precision, s),
                     "azimuth fused launch");
         } else {
-            HIP_TRY(sar::launch_line(LineOp::Forward, Na, in, out, Nr, nullptr, P->tw_a, 1.f, nullptr, s),
+            HIP_TRY(sar::launch_line(LineOp::Forward, Na, in, out, Nr, nullptr, P->tw_a, 1.f, nullptr, P->p.precision, s),
                     "azimuth FFT launch");
             HIP_TRY(sar::launch_rowmul(out, out, Nr, Na, P->Ha, s), "azimuth multiply launch");
-            HIP_TRY(sar::launch_line(LineOp::Inverse, Na, out, out, Nr, nullptr, P->tw_a, 1.f, nullptr, s),
+            HIP_TRY(sar::launch_line(LineOp::Inverse, Na, out, out, Nr, nullptr, P->tw_a, 1.f, nullptr, P->p.precision, s),
                     "azimuth IFFT launch");
         }
         return SAR_OK;
     }
     const sar::RcmcHost rh = rcmc_host(P);
-    HIP_TRY(sar::launch_line(LineOp::Forward, Na, in, work, Nr, nullptr, P->tw_a, 1.f, nullptr, s),
+    HIP_TRY(sar::launch_line(LineOp::Forward, Na, in, work, Nr, nullptr, P->tw_a, 1.f, nullptr, P->p.precision, s),
             "azimuth FFT launch");
     if (P->p.schedule == SAR_FUSED) {
-        HIP_TRY(sar::launch_line(LineOp::RcmcAz, Na, work, out, Nr, nullptr, P->tw_a, 1.f, &rh, s),
+        HIP_TRY(sar::launch_line(LineOp::RcmcAz, Na, work, out, Nr, nullptr, P->tw_a, 1.f, &rh, P->p.precision, s),
                 "RCMC+azimuth launch");
     } else {
         HIP_TRY(sar::launch_rcmc_interp(work, out, Na, rh, s), "RCMC launch");
         HIP_TRY(sar::launch_az_phase(out, out, Na, rh, 1.0f / (float)Na, s), "azimuth phase launch");
-        HIP_TRY(sar::launch_line(LineOp::Inverse, Na, out, out, Nr, nullptr, P->tw_a, 1.f, nullptr, s),
+        HIP_TRY(sar::launch_line(LineOp::Inverse, Na, out, out, Nr, nullptr, P->tw_a, 1.f, nullptr, P->p.precision, s),
                 "azimuth IFFT launch");
     }
     return SAR_OK;
@@ -403,7 +401,7 @@ sar_status sar_fft_lines(sar_plan_t P, int32_t axis, int32_t inverse, const void
     const size_t n = (size_t)lines * N * 8;
     if (in != out && overlap(in, n, out, n)) return fail(SAR_ERR_ALIAS, "in and out partially overlap");
     HIP_TRY(sar::launch_line(inverse ? LineOp::Inverse : LineOp::Forward, N, in, out, lines, nullptr,
-                             axis == 0 ? P->tw_r : P->tw_a, inverse ? 1.0f / (float)N : 1.0f, nullptr,
+                             axis == 0 ? P->tw_r : P->tw_a, inverse ? 1.0f / (float)N : 1.0f, nullptr, P->p.precision,
                              (hipStream_t)stream),
             "FFT launch");
     return SAR_OK;
@@ -430,13 +428,13 @@ sar_status sar_rcmc_azimuth(sar_plan_t P, const void* A, void* out, void* stream
     const sar::RcmcHost rh = rcmc_host(P);
     hipStream_t s = (hipStream_t)stream;
     if (P->p.schedule == SAR_FUSED) {
-        HIP_TRY(sar::launch_line(LineOp::RcmcAz, P->p.Na, A, out, P->p.Nr, nullptr, P->tw_a, 1.f, &rh, s),
+        HIP_TRY(sar::launch_line(LineOp::RcmcAz, P->p.Na, A, out, P->p.Nr, nullptr, P->tw_a, 1.f, &rh, P->p.precision, s),
                 "RCMC+azimuth launch");
     } else {
         HIP_TRY(sar::launch_rcmc_interp(A, out, P->p.Na, rh, s), "RCMC launch");
         HIP_TRY(sar::launch_az_phase(out, out, P->p.Na, rh, 1.0f / (float)P->p.Na, s), "phase launch");
         HIP_TRY(sar::launch_line(LineOp::Inverse, P->p.Na, out, out, P->p.Nr, nullptr, P->tw_a, 1.f,
-                                 nullptr, s),
+                                 nullptr, P->p.precision, s),
                 "azimuth IFFT launch");
     }
     return SAR_OK;

@@ -33,8 +33,9 @@ struct RcmcHost {
 //  Fused:   out = IFFT(FFT(in) * H)   (H includes 1/n)
 //  Forward: out = FFT(in) * scale;  Inverse: out = unscaled IFFT(in) * scale
 //  RcmcAz:  out[n] = IFFT(RCMC(in)[n] * phase / n), rh required, lines = rh->nr
+//  prec: 0 FP32 butterflies, 1 split FP16 / 2 split BF16 radix-16 butterflies on MFMA
 hipError_t launch_line(LineOp op, int n, const void* in, void* out, int lines, const void* H,
-                       const void* tw, float scale, const RcmcHost* rh, hipStream_t s);
+                       const void* tw, float scale, const RcmcHost* rh, int prec, hipStream_t s);
 int twiddle_table_size(int n);
 
 hipError_t launch_rowmul(const void* in, void* out, int rows, int n, const void* H, hipStream_t s);

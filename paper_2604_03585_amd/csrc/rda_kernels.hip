@@ -22,6 +22,7 @@
 #include <cstdint>
 
 #include "fft_line.hpp"
+#include "mfma_fft.hpp"
 #include "rda_internal.h"
 
 namespace sar {
@@ -109,6 +110,23 @@ template <int N> struct LineLaunch {
     static constexpr int LDS_BYTES = LPW * LineGeom<N>::LDS * (int)sizeof(float2);
 };
 
+// Line transform in the requested butterfly precision: FP32 VALU passes, or
+// split FP16 / BF16 radix-16 passes on MFMA (twiddles and filters in FP32).
+template <int N, bool INV, int PREC, class F = NoOp>
+__device__ __forceinline__ void fft_any(float2 (&x)[line_e(N)], float2* __restrict__ lds,
+                                        const float2* __restrict__ tw, int sub, int t,
+                                        F&& before_last = F())
+{
+    if constexpr (PREC == PREC_FP32) {
+        fft_line<N, INV>(x, lds, tw, t, before_last);
+    } else {
+        using L = LineLaunch<N>;
+        before_last();
+        fft_line_mfma<N, INV, PREC, L::LPW, L::BLOCK>(x, (float*)(lds - sub * LineGeom<N>::LDS),
+                                                      tw, sub, t);
+    }
+}
+
 // XCD-aware line order: gfx950 hands workgroup b to XCD (b mod 8); giving each
 // XCD a contiguous run of line groups keeps neighbouring lines in one L2.
 __device__ __forceinline__ int xcd_group(int b, int groups)
@@ -138,7 +156,7 @@ enum LineKind { LK_FUSED = 0, LK_FWD = 1, LK_INV = 2 };
 
 //  LK_FUSED: out = IFFT(FFT(in) * H)      (H carries the 1/N)
 //  LK_FWD:   out = FFT(in) * scale;  LK_INV: out = IFFT_unscaled(in) * scale
-template <int N, int KIND>
+template <int N, int KIND, int PREC>
 __global__ __launch_bounds__(LineLaunch<N>::BLOCK) void
 k_line(const float2* in, float2* out, int lines, const float2* __restrict__ H,
        const float2* __restrict__ tw, float scale)
@@ -159,15 +177,15 @@ k_line(const float2* in, float2* out, int lines, const float2* __restrict__ H,
     if constexpr (KIND == LK_FUSED) {
         // the filter is requested just before the last forward pass
         float2 h[E];
-        fft_line<N, false>(x, lds, tw, t, [&] {
+        fft_any<N, false, PREC>(x, lds, tw, sub, t, [&] {
 #pragma unroll
             for (int m = 0; m < E; ++m) h[m] = H[t + m * L::T];
         });
 #pragma unroll
         for (int m = 0; m < E; ++m) x[m] = c_mul(x[m], h[m]);
-        fft_line<N, true>(x, lds, tw, t);
+        fft_any<N, true, PREC>(x, lds, tw, sub, t);
     } else {
-        fft_line<N, KIND == LK_INV>(x, lds, tw, t);
+        fft_any<N, KIND == LK_INV, PREC>(x, lds, tw, sub, t);
         if (scale != 1.0f) {
 #pragma unroll
             for (int m = 0; m < E; ++m) x[m] = c_scale(x[m], scale);
@@ -480,7 +498,7 @@ __device__ __forceinline__ void rcmc_row(float2 (&x)[line_e(N)], const float2* _
     }
 }
 
-template <int N, int TAPS>
+template <int N, int TAPS, int PREC>
 __global__ __launch_bounds__(LineLaunch<N>::BLOCK) void
 k_rcmc_az(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
                const float2* __restrict__ tw)
@@ -529,7 +547,7 @@ k_rcmc_az(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
         rcmc_row<N, true>(x, A, t, ra.nr, xs, i0s, ph, tab);
     }
     if constexpr (TAPS != 0) __syncthreads();     // table reads done before LDS reuse
-    fft_line<N, true>(x, lds, tw, t);
+    fft_any<N, true, PREC>(x, lds, tw, sub, t);
     if (live) store_line<N>(x, out + (size_t)n * N, t);
 }
 
@@ -626,7 +644,7 @@ __device__ __forceinline__ void rcmc_rows2(float2 (&xa)[line_e(N)], float2 (&xb)
     }
 }
 
-template <int N>
+template <int N, int PREC>
 __global__ __launch_bounds__(LineLaunch<N>::BLOCK) void
 k_rcmc_az2(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
            const float2* __restrict__ tw)
@@ -657,9 +675,9 @@ k_rcmc_az2(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
             rcmc_rows2<N, true>(xa, xb, A, ra, n, t, tab);
     }
     __syncthreads();                              // table reads done before LDS reuse
-    fft_line<N, true>(xa, lds, tw, t);
+    fft_any<N, true, PREC>(xa, lds, tw, sub, t);
     if (live) store_line<N>(xa, out + (size_t)n * N, t);
-    fft_line<N, true>(xb, lds, tw, t);
+    fft_any<N, true, PREC>(xb, lds, tw, sub, t);
     if (live) store_line<N>(xb, out + (size_t)(n + 1) * N, t);
 }
 
@@ -717,82 +735,87 @@ static int grid_for(long long work, int per_block)
     return (int)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
-template <int N>
+template <int N, int PREC>
 static hipError_t set_lds_limit()
 {
     using L = LineLaunch<N>;
-    constexpr int rcmc_bytes = L::LDS_BYTES;
-    hipError_t e = hipSuccess;
-    if (L::LDS_BYTES > 64 * 1024) {
-        e = hipFuncSetAttribute((const void*)k_line<N, LK_FUSED>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, L::LDS_BYTES);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_line<N, LK_FWD>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, L::LDS_BYTES);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_line<N, LK_INV>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, L::LDS_BYTES);
+    if (L::LDS_BYTES <= 64 * 1024) return hipSuccess;
+    const void* fns[] = {(const void*)k_line<N, LK_FUSED, PREC>, (const void*)k_line<N, LK_FWD, PREC>,
+                         (const void*)k_line<N, LK_INV, PREC>, (const void*)k_rcmc_az<N, 0, PREC>,
+                         (const void*)k_rcmc_az<N, 8, PREC>, (const void*)k_rcmc_az2<N, PREC>};
+    for (const void* f : fns) {
+        const hipError_t e =
+            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, L::LDS_BYTES);
+        if (e != hipSuccess) return e;
     }
-    if (e == hipSuccess && rcmc_bytes > 64 * 1024) {
-        e = hipFuncSetAttribute((const void*)k_rcmc_az<N, 0>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, rcmc_bytes);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_rcmc_az<N, 8>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, rcmc_bytes);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_rcmc_az2<N>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, rcmc_bytes);
-    }
-    return e;
+    return hipSuccess;
 }
 
-template <int N, int KIND>
+template <int N, int KIND, int PREC>
 static hipError_t launch_k_line(const float2* in, float2* out, int lines, const float2* H,
                                 const float2* tw, float scale, hipStream_t s)
 {
     using L = LineLaunch<N>;
     const int groups = (lines + L::LPW - 1) / L::LPW;
     if (groups == 0) return hipSuccess;
-    const int grid = groups;
-    hipLaunchKernelGGL((k_line<N, KIND>), dim3(grid), dim3(L::BLOCK), L::LDS_BYTES, s, in, out,
-                       lines, H, tw, scale);
+    hipLaunchKernelGGL((k_line<N, KIND, PREC>), dim3(groups), dim3(L::BLOCK), L::LDS_BYTES, s, in,
+                       out, lines, H, tw, scale);
     return hipGetLastError();
 }
 
-template <int N>
+template <int N, int PREC>
 static hipError_t launch_line_n(LineOp op, const float2* in, float2* out, int lines,
                                 const float2* H, const float2* tw, float scale,
                                 const RcmcArgs* ra, int taps, hipStream_t s)
 {
     using L = LineLaunch<N>;
-    static const hipError_t attr = set_lds_limit<N>();
+    static const hipError_t attr = set_lds_limit<N, PREC>();
     if (attr != hipSuccess) return attr;
     switch (op) {
-    case LineOp::Fused: return launch_k_line<N, LK_FUSED>(in, out, lines, H, tw, 1.0f, s);
-    case LineOp::Forward: return launch_k_line<N, LK_FWD>(in, out, lines, nullptr, tw, scale, s);
-    case LineOp::Inverse: return launch_k_line<N, LK_INV>(in, out, lines, nullptr, tw, scale, s);
+    case LineOp::Fused: return launch_k_line<N, LK_FUSED, PREC>(in, out, lines, H, tw, 1.0f, s);
+    case LineOp::Forward: return launch_k_line<N, LK_FWD, PREC>(in, out, lines, nullptr, tw, scale, s);
+    case LineOp::Inverse: return launch_k_line<N, LK_INV, PREC>(in, out, lines, nullptr, tw, scale, s);
     case LineOp::RcmcAz: {
         const int groups = (lines + L::LPW - 1) / L::LPW;
         if (groups == 0) return hipSuccess;
         static_assert(L::LDS_BYTES >= RCMC_TAB * (int)sizeof(float), "table fits the line LDS");
         if (taps == 8 && ra->stretch_max < 0.5 && (lines & 1) == 0) {
             const int g2 = (lines / 2 + L::LPW - 1) / L::LPW;
-            hipLaunchKernelGGL((k_rcmc_az2<N>), dim3(g2), dim3(L::BLOCK), L::LDS_BYTES, s, in, out,
-                               *ra, tw);
+            hipLaunchKernelGGL((k_rcmc_az2<N, PREC>), dim3(g2), dim3(L::BLOCK), L::LDS_BYTES, s, in,
+                               out, *ra, tw);
         } else if (taps == 8)
-            hipLaunchKernelGGL((k_rcmc_az<N, 8>), dim3(groups), dim3(L::BLOCK), L::LDS_BYTES, s, in,
-                               out, *ra, tw);
+            hipLaunchKernelGGL((k_rcmc_az<N, 8, PREC>), dim3(groups), dim3(L::BLOCK), L::LDS_BYTES,
+                               s, in, out, *ra, tw);
         else
-            hipLaunchKernelGGL((k_rcmc_az<N, 0>), dim3(groups), dim3(L::BLOCK), L::LDS_BYTES, s, in,
-                               out, *ra, tw);
+            hipLaunchKernelGGL((k_rcmc_az<N, 0, PREC>), dim3(groups), dim3(L::BLOCK), L::LDS_BYTES,
+                               s, in, out, *ra, tw);
         return hipGetLastError();
     }
     }
     return hipErrorInvalidValue;
 }
 
+template <int PREC>
+static hipError_t launch_line_prec(LineOp op, int n, const float2* i, float2* o, int lines,
+                                   const float2* h, const float2* w, float scale,
+                                   const RcmcArgs* ra, int taps, hipStream_t s)
+{
+    switch (n) {
+    case 64: return launch_line_n<64, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
+    case 128: return launch_line_n<128, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
+    case 256: return launch_line_n<256, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
+    case 512: return launch_line_n<512, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
+    case 1024: return launch_line_n<1024, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
+    case 2048: return launch_line_n<2048, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
+    case 4096: return launch_line_n<4096, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
+    case 8192: return launch_line_n<8192, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
+    case 16384: return launch_line_n<16384, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_line(LineOp op, int n, const void* in, void* out, int lines, const void* H,
-                       const void* tw, float scale, const RcmcHost* rh, hipStream_t s)
+                       const void* tw, float scale, const RcmcHost* rh, int prec, hipStream_t s)
 {
     RcmcArgs ra{};
     int taps = 0;
@@ -804,16 +827,10 @@ hipError_t launch_line(LineOp op, int n, const void* in, void* out, int lines, c
     auto o = (float2*)out;
     auto h = (const float2*)H;
     auto w = (const float2*)tw;
-    switch (n) {
-    case 64: return launch_line_n<64>(op, i, o, lines, h, w, scale, &ra, taps, s);
-    case 128: return launch_line_n<128>(op, i, o, lines, h, w, scale, &ra, taps, s);
-    case 256: return launch_line_n<256>(op, i, o, lines, h, w, scale, &ra, taps, s);
-    case 512: return launch_line_n<512>(op, i, o, lines, h, w, scale, &ra, taps, s);
-    case 1024: return launch_line_n<1024>(op, i, o, lines, h, w, scale, &ra, taps, s);
-    case 2048: return launch_line_n<2048>(op, i, o, lines, h, w, scale, &ra, taps, s);
-    case 4096: return launch_line_n<4096>(op, i, o, lines, h, w, scale, &ra, taps, s);
-    case 8192: return launch_line_n<8192>(op, i, o, lines, h, w, scale, &ra, taps, s);
-    case 16384: return launch_line_n<16384>(op, i, o, lines, h, w, scale, &ra, taps, s);
+    switch (prec) {
+    case PREC_FP32: return launch_line_prec<PREC_FP32>(op, n, i, o, lines, h, w, scale, &ra, taps, s);
+    case PREC_F16: return launch_line_prec<PREC_F16>(op, n, i, o, lines, h, w, scale, &ra, taps, s);
+    case PREC_BF16: return launch_line_prec<PREC_BF16>(op, n, i, o, lines, h, w, scale, &ra, taps, s);
     default: return hipErrorInvalidValue;
     }
 }
