@@ -96,6 +96,13 @@ struct sar_plan_s {
     double stretch_max = 0.0;     // hyperbolic: 1/D - 1 at |f| = 1/2
 };
 
+namespace sar {
+PlanTables plan_tables(const sar_plan_s* P)
+{
+    return PlanTables{P->Hr, P->Ha, P->tw_r, P->tw_a};
+}
+}  // namespace sar
+
 namespace {
 
 sar_status validate_params(const sar_params* p)

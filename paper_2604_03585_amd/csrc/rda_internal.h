@@ -8,6 +8,8 @@
 
 #include "sar_rda.h"
 
+struct sar_plan_s;
+
 namespace sar {
 
 // Record a message for sar_last_error() on this thread and return `st`.
@@ -15,6 +17,26 @@ sar_status set_error(sar_status st, const char* fmt, ...);
 void clear_error();
 
 enum class LineOp { Fused, Forward, Inverse, RcmcAz };
+
+// One scene's share of a batched line launch: `lines` lines of `in` -> `out`
+// with this scene's filter and twiddles; group_begin is the index of its
+// first line group in the launch (tasks sorted by it).
+struct LineTask {
+    const float2* in;
+    float2* out;
+    const float2* H;
+    const float2* tw;
+    int lines;
+    int group_begin;
+};
+
+// One matrix of a batched corner turn (rows x cols -> cols x rows).
+struct TurnTask {
+    const float2* in;
+    float2* out;
+    int rows, cols;
+    int tile_begin;
+};
 
 // Host-side description of the hyperbolic azimuth tables and RCMC kernel.
 struct RcmcHost {
@@ -37,6 +59,22 @@ struct RcmcHost {
 hipError_t launch_line(LineOp op, int n, const void* in, void* out, int lines, const void* H,
                        const void* tw, float scale, const RcmcHost* rh, int prec, hipStream_t s);
 int twiddle_table_size(int n);
+
+// Batched launches (kind: 0 fused, 1 forward, 2 inverse; tasks in device memory).
+hipError_t launch_line_batch(int kind, int n, const void* tasks, int ntasks, int total_groups,
+                             float scale, int prec, hipStream_t s);
+hipError_t launch_corner_turn_batch(const void* tasks, int ntasks, int total_tiles, hipStream_t s);
+int line_groups(int n, int lines);        // line groups of `lines` lines of length n
+
+// Device tables of a plan (for the batch runtime).
+struct PlanTables {
+    const void* Hr;
+    const void* Ha;
+    const void* tw_r;
+    const void* tw_a;
+};
+PlanTables plan_tables(const sar_plan_s* P);
+int turn_tiles(int rows, int cols);       // 64 x 64 tiles of a corner turn
 
 hipError_t launch_rowmul(const void* in, void* out, int rows, int n, const void* H, hipStream_t s);
 hipError_t launch_corner_turn(const void* in, void* out, int rows, int cols, hipStream_t s);

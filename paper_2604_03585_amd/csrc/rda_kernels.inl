@@ -1,5 +1,8 @@
-// rda_kernels.hip -- gfx950 kernels of the Range Doppler Algorithm and their
-// launchers.  Every kernel is written for wave64 CDNA4; lines are kept in
+// rda_kernels.inl -- gfx950 kernels of the Range Doppler Algorithm and their
+// launchers.  Compiled in four parts (rda_part_*.hip, SAR_PART = 0..3) so that
+// the template instantiations build in parallel: part 0 holds the table
+// generators, the non-line kernels and the dispatcher, parts 1-3 the line
+// and RCMC kernels for FP32, split-FP16 and split-BF16 butterflies.  Every kernel is written for wave64 CDNA4; lines are kept in
 // registers (16 complex64 per thread) and LDS between radix passes.
 //
 // Kernels (paper: arXiv 2604.03585):
@@ -27,6 +30,7 @@
 
 namespace sar {
 
+#if SAR_PART == 0
 // ===================================================== FP64 generators
 // exp(-2 pi i * num / den) in FP64, num reduced exactly mod den first.
 __device__ __forceinline__ float2 twiddle_fp64(long long num, long long den)
@@ -102,6 +106,8 @@ __global__ void k_gen_hyper_tables(double* __restrict__ stretch, double* __restr
     rate[k] = 2.0 * D / lam;
 }
 
+#endif  // SAR_PART == 0
+
 // ===================================================== line kernels
 template <int N> struct LineLaunch {
     static constexpr int T = LineGeom<N>::T;
@@ -156,16 +162,17 @@ enum LineKind { LK_FUSED = 0, LK_FWD = 1, LK_INV = 2 };
 
 //  LK_FUSED: out = IFFT(FFT(in) * H)      (H carries the 1/N)
 //  LK_FWD:   out = FFT(in) * scale;  LK_INV: out = IFFT_unscaled(in) * scale
+// One group of LPW lines starting at line g * LPW of `in` / `out`.
 template <int N, int KIND, int PREC>
-__global__ __launch_bounds__(LineLaunch<N>::BLOCK) void
-k_line(const float2* in, float2* out, int lines, const float2* __restrict__ H,
-       const float2* __restrict__ tw, float scale)
+__device__ __forceinline__ void line_group(const float2* in, float2* out, int lines,
+                                           const float2* __restrict__ H,
+                                           const float2* __restrict__ tw, float scale, int g,
+                                           float2* smem)
 {
     using L = LineLaunch<N>;
     constexpr int E = line_e(N);
-    extern __shared__ float2 smem[];
     const int sub = threadIdx.x / L::T, t = threadIdx.x % L::T;
-    const int line = blockIdx.x * L::LPW + sub;
+    const int line = g * L::LPW + sub;
     const bool live = line < lines;
     float2* lds = smem + sub * LineGeom<N>::LDS;
     float2 x[E];
@@ -194,6 +201,39 @@ k_line(const float2* in, float2* out, int lines, const float2* __restrict__ H,
     if (live) store_line<N>(x, out + (size_t)line * N, t);
 }
 
+template <int N, int KIND, int PREC>
+__global__ __launch_bounds__(LineLaunch<N>::BLOCK) void
+k_line(const float2* in, float2* out, int lines, const float2* __restrict__ H,
+       const float2* __restrict__ tw, float scale)
+{
+    extern __shared__ float2 smem[];
+    line_group<N, KIND, PREC>(in, out, lines, H, tw, scale, blockIdx.x, smem);
+}
+
+// Batched form: the line groups of many scenes (tasks) in one launch.  The
+// grid covers min(total groups, resident capacity) workgroups, each walking
+// groups gg = blockIdx.x, + gridDim.x, ...; the task of a group is found by
+// binary search over the tasks' first-group indices (sorted).
+template <int N, int KIND, int PREC>
+__global__ __launch_bounds__(LineLaunch<N>::BLOCK) void
+k_line_batch(const LineTask* __restrict__ tasks, int ntasks, int total_groups, float scale)
+{
+    extern __shared__ float2 smem[];
+    for (int gg = blockIdx.x; gg < total_groups; gg += gridDim.x) {
+        int lo = 0, hi = ntasks - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tasks[mid].group_begin <= gg) lo = mid;
+            else hi = mid - 1;
+        }
+        const LineTask tk = tasks[lo];
+        line_group<N, KIND, PREC>(tk.in, tk.out, tk.lines, tk.H, tk.tw, scale,
+                                  gg - tk.group_begin, smem);
+        __syncthreads();                          // LDS reuse by the next group
+    }
+}
+
+#if SAR_PART == 0
 // out[r][k] = in[r][k] * H[k]  (unfused comparator's multiply dispatch)
 __global__ __launch_bounds__(256) void k_rowmul(const float4* in, float4* out, long long n_pairs,
                                                 int n, const float2* __restrict__ H)
@@ -236,6 +276,42 @@ __global__ __launch_bounds__(256) void k_corner_turn(const float2* __restrict__ 
     }
 }
 
+// Batched corner turn: the 64 x 64 tiles of many matrices in one launch.
+__global__ __launch_bounds__(256) void k_corner_turn_batch(const TurnTask* __restrict__ tasks,
+                                                           int ntasks, int total_tiles)
+{
+    __shared__ float2 tile[TT][TT + 1];
+    for (int gt = blockIdx.x; gt < total_tiles; gt += gridDim.x) {
+        int lo = 0, hi = ntasks - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tasks[mid].tile_begin <= gt) lo = mid;
+            else hi = mid - 1;
+        }
+        const TurnTask tk = tasks[lo];
+        const int b = gt - tk.tile_begin;
+        const int tiles_c = (tk.cols + TT - 1) / TT;
+        const int r0 = (b / tiles_c) * TT, c0 = (b % tiles_c) * TT;
+        const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+        for (int i = 0; i < TT / 4; ++i) {
+            const int r = ty + 4 * i;
+            if (r0 + r < tk.rows && c0 + tx < tk.cols)
+                tile[r][tx] = tk.in[(size_t)(r0 + r) * tk.cols + c0 + tx];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < TT / 4; ++i) {
+            const int c = ty + 4 * i;
+            if (c0 + c < tk.cols && r0 + tx < tk.rows)
+                tk.out[(size_t)(c0 + c) * tk.rows + r0 + tx] = tile[tx][c];
+        }
+        __syncthreads();
+    }
+}
+
+#endif  // SAR_PART == 0
+
 // ===================================================== RCMC
 // The 8-tap Kaiser-windowed sinc (taps t = -3..4 about floor(p), x = p -
 // floor(p), weights normalised to unit sum) depends on x alone.  Its eight
@@ -250,6 +326,7 @@ __global__ __launch_bounds__(256) void k_corner_turn(const float2* __restrict__ 
 constexpr int RCMC_INTERVALS = 64;
 constexpr int RCMC_TAB = 8 * 4 * RCMC_INTERVALS;
 
+#if SAR_PART == 0
 __device__ double i0_fp64(double y)
 {
     const double q = 0.25 * y * y;
@@ -313,6 +390,8 @@ __global__ void k_gen_rcmc_table(float* __restrict__ tab, double beta)
         for (int j = 0; j < 4; ++j) tab[(t * 4 + j) * RCMC_INTERVALS + b] = (float)cf[j];
     }
 }
+
+#endif  // SAR_PART == 0
 
 struct RcmcArgs {
     const double* stretch;   // 1/D_k - 1 per Doppler bin
@@ -681,6 +760,7 @@ k_rcmc_az2(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
     if (live) store_line<N>(xb, out + (size_t)(n + 1) * N, t);
 }
 
+#if SAR_PART == 0
 // Unfused comparator: RCMC interpolation alone (grid-stride, one sample per
 // thread per iteration).
 template <int TAPS>
@@ -713,6 +793,8 @@ __global__ __launch_bounds__(256) void k_az_phase(const float2* __restrict__ in,
     }
 }
 
+#endif  // SAR_PART == 0
+
 // ===================================================== launchers
 static RcmcArgs make_rcmc_args(const RcmcHost& rh)
 {
@@ -728,7 +810,7 @@ static RcmcArgs make_rcmc_args(const RcmcHost& rh)
     return ra;
 }
 
-static int grid_for(long long work, int per_block)
+[[maybe_unused]] static int grid_for(long long work, int per_block)
 {
     long long g = (work + per_block - 1) / per_block;
     const long long cap = 256LL * 64;   // grid-stride kernels: 64 workgroups per CU
@@ -742,7 +824,10 @@ static hipError_t set_lds_limit()
     if (L::LDS_BYTES <= 64 * 1024) return hipSuccess;
     const void* fns[] = {(const void*)k_line<N, LK_FUSED, PREC>, (const void*)k_line<N, LK_FWD, PREC>,
                          (const void*)k_line<N, LK_INV, PREC>, (const void*)k_rcmc_az<N, 0, PREC>,
-                         (const void*)k_rcmc_az<N, 8, PREC>, (const void*)k_rcmc_az2<N, PREC>};
+                         (const void*)k_rcmc_az<N, 8, PREC>, (const void*)k_rcmc_az2<N, PREC>,
+                         (const void*)k_line_batch<N, LK_FUSED, PREC>,
+                         (const void*)k_line_batch<N, LK_FWD, PREC>,
+                         (const void*)k_line_batch<N, LK_INV, PREC>};
     for (const void* f : fns) {
         const hipError_t e =
             hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, L::LDS_BYTES);
@@ -795,6 +880,53 @@ static hipError_t launch_line_n(LineOp op, const float2* in, float2* out, int li
     return hipErrorInvalidValue;
 }
 
+template <int N, int PREC>
+static hipError_t launch_line_batch_n(int kind, const LineTask* tasks, int ntasks, int total_groups,
+                                      float scale, hipStream_t s)
+{
+    using L = LineLaunch<N>;
+    static const hipError_t attr = set_lds_limit<N, PREC>();
+    if (attr != hipSuccess) return attr;
+    if (total_groups == 0) return hipSuccess;
+    // resident capacity: LDS-limited workgroups per CU x 256 CUs
+    const int per_cu = (160 * 1024) / L::LDS_BYTES;
+    const int cap = (per_cu < 1 ? 1 : per_cu) * 256 * 2;
+    const int grid = total_groups < cap ? total_groups : cap;
+    switch (kind) {
+    case LK_FUSED:
+        hipLaunchKernelGGL((k_line_batch<N, LK_FUSED, PREC>), dim3(grid), dim3(L::BLOCK),
+                           L::LDS_BYTES, s, tasks, ntasks, total_groups, scale);
+        break;
+    case LK_FWD:
+        hipLaunchKernelGGL((k_line_batch<N, LK_FWD, PREC>), dim3(grid), dim3(L::BLOCK),
+                           L::LDS_BYTES, s, tasks, ntasks, total_groups, scale);
+        break;
+    default:
+        hipLaunchKernelGGL((k_line_batch<N, LK_INV, PREC>), dim3(grid), dim3(L::BLOCK),
+                           L::LDS_BYTES, s, tasks, ntasks, total_groups, scale);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_line_batch_prec(int kind, int n, const LineTask* tasks, int ntasks,
+                                         int total_groups, float scale, hipStream_t s)
+{
+    switch (n) {
+    case 64: return launch_line_batch_n<64, PREC>(kind, tasks, ntasks, total_groups, scale, s);
+    case 128: return launch_line_batch_n<128, PREC>(kind, tasks, ntasks, total_groups, scale, s);
+    case 256: return launch_line_batch_n<256, PREC>(kind, tasks, ntasks, total_groups, scale, s);
+    case 512: return launch_line_batch_n<512, PREC>(kind, tasks, ntasks, total_groups, scale, s);
+    case 1024: return launch_line_batch_n<1024, PREC>(kind, tasks, ntasks, total_groups, scale, s);
+    case 2048: return launch_line_batch_n<2048, PREC>(kind, tasks, ntasks, total_groups, scale, s);
+    case 4096: return launch_line_batch_n<4096, PREC>(kind, tasks, ntasks, total_groups, scale, s);
+    case 8192: return launch_line_batch_n<8192, PREC>(kind, tasks, ntasks, total_groups, scale, s);
+    case 16384: return launch_line_batch_n<16384, PREC>(kind, tasks, ntasks, total_groups, scale, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <int PREC>
 static hipError_t launch_line_prec(LineOp op, int n, const float2* i, float2* o, int lines,
                                    const float2* h, const float2* w, float scale,
@@ -814,6 +946,50 @@ static hipError_t launch_line_prec(LineOp op, int n, const float2* i, float2* o,
     }
 }
 
+// One instantiation of launch_line_prec / launch_line_batch_prec per part
+// (defined in parts 1-3).
+hipError_t launch_line_batch_p1(int, int, const LineTask*, int, int, float, hipStream_t);
+hipError_t launch_line_batch_p2(int, int, const LineTask*, int, int, float, hipStream_t);
+hipError_t launch_line_batch_p3(int, int, const LineTask*, int, int, float, hipStream_t);
+hipError_t launch_line_fp32(LineOp, int, const float2*, float2*, int, const float2*, const float2*,
+                            float, const RcmcArgs*, int, hipStream_t);
+hipError_t launch_line_f16(LineOp, int, const float2*, float2*, int, const float2*, const float2*,
+                           float, const RcmcArgs*, int, hipStream_t);
+hipError_t launch_line_bf16(LineOp, int, const float2*, float2*, int, const float2*, const float2*,
+                            float, const RcmcArgs*, int, hipStream_t);
+
+#if SAR_PART >= 1
+hipError_t SAR_LINE_BATCH_FN(int kind, int n, const LineTask* tasks, int ntasks, int total_groups,
+                             float scale, hipStream_t s)
+{
+    return launch_line_batch_prec<SAR_PART - 1>(kind, n, tasks, ntasks, total_groups, scale, s);
+}
+#endif
+
+#if SAR_PART == 1
+hipError_t launch_line_fp32(LineOp op, int n, const float2* i, float2* o, int lines,
+                            const float2* h, const float2* w, float scale, const RcmcArgs* ra,
+                            int taps, hipStream_t s)
+{
+    return launch_line_prec<PREC_FP32>(op, n, i, o, lines, h, w, scale, ra, taps, s);
+}
+#elif SAR_PART == 2
+hipError_t launch_line_f16(LineOp op, int n, const float2* i, float2* o, int lines,
+                           const float2* h, const float2* w, float scale, const RcmcArgs* ra,
+                           int taps, hipStream_t s)
+{
+    return launch_line_prec<PREC_F16>(op, n, i, o, lines, h, w, scale, ra, taps, s);
+}
+#elif SAR_PART == 3
+hipError_t launch_line_bf16(LineOp op, int n, const float2* i, float2* o, int lines,
+                            const float2* h, const float2* w, float scale, const RcmcArgs* ra,
+                            int taps, hipStream_t s)
+{
+    return launch_line_prec<PREC_BF16>(op, n, i, o, lines, h, w, scale, ra, taps, s);
+}
+#endif
+
+#if SAR_PART == 0
 hipError_t launch_line(LineOp op, int n, const void* in, void* out, int lines, const void* H,
                        const void* tw, float scale, const RcmcHost* rh, int prec, hipStream_t s)
 {
@@ -828,12 +1004,42 @@ hipError_t launch_line(LineOp op, int n, const void* in, void* out, int lines, c
     auto h = (const float2*)H;
     auto w = (const float2*)tw;
     switch (prec) {
-    case PREC_FP32: return launch_line_prec<PREC_FP32>(op, n, i, o, lines, h, w, scale, &ra, taps, s);
-    case PREC_F16: return launch_line_prec<PREC_F16>(op, n, i, o, lines, h, w, scale, &ra, taps, s);
-    case PREC_BF16: return launch_line_prec<PREC_BF16>(op, n, i, o, lines, h, w, scale, &ra, taps, s);
+    case PREC_FP32: return launch_line_fp32(op, n, i, o, lines, h, w, scale, &ra, taps, s);
+    case PREC_F16: return launch_line_f16(op, n, i, o, lines, h, w, scale, &ra, taps, s);
+    case PREC_BF16: return launch_line_bf16(op, n, i, o, lines, h, w, scale, &ra, taps, s);
     default: return hipErrorInvalidValue;
     }
 }
+
+hipError_t launch_line_batch(int kind, int n, const void* tasks, int ntasks, int total_groups,
+                             float scale, int prec, hipStream_t s)
+{
+    const LineTask* t = (const LineTask*)tasks;
+    switch (prec) {
+    case PREC_FP32: return launch_line_batch_p1(kind, n, t, ntasks, total_groups, scale, s);
+    case PREC_F16: return launch_line_batch_p2(kind, n, t, ntasks, total_groups, scale, s);
+    case PREC_BF16: return launch_line_batch_p3(kind, n, t, ntasks, total_groups, scale, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_corner_turn_batch(const void* tasks, int ntasks, int total_tiles, hipStream_t s)
+{
+    if (total_tiles == 0) return hipSuccess;
+    const int grid = total_tiles < 256 * 16 ? total_tiles : 256 * 16;
+    hipLaunchKernelGGL(k_corner_turn_batch, dim3(grid), dim3(256), 0, s, (const TurnTask*)tasks,
+                       ntasks, total_tiles);
+    return hipGetLastError();
+}
+
+int line_groups(int n, int lines)
+{
+    const int T = n / line_e(n);
+    const int lpw = T >= 256 ? 1 : 256 / T;
+    return (lines + lpw - 1) / lpw;
+}
+
+int turn_tiles(int rows, int cols) { return ((rows + TT - 1) / TT) * ((cols + TT - 1) / TT); }
 
 int twiddle_table_size(int n)
 {
@@ -923,5 +1129,7 @@ hipError_t launch_gen_hyper_tables(double* stretch, double* rate, int na, double
                        na, lam, v);
     return hipGetLastError();
 }
+
+#endif  // SAR_PART == 0
 
 }  // namespace sar
