@@ -194,10 +194,51 @@ sar_status sar_batch_execute(sar_batch_t batch, const void* const* raw_dev,
 
 void sar_batch_destroy(sar_batch_t batch);
 
-/* Measure candidate kernel configurations for the plan's sizes on the
- * current device and store the winners in a JSON cache at cache_path
- * (NULL: $SAR_AUTOTUNE_CACHE).  Later plans read the cache. Synchronous. */
+/* ---- autotuner (the batching/serving pattern: measured kernel choices) ----
+ *
+ * Kernel variants are chosen per (kind, line length N, precision); every
+ * variant computes the same result, they differ in scheduling only:
+ *   kind 0 fused FFT*H*IFFT, 1 forward FFT, 2 inverse FFT line kernels:
+ *          variant bit 0 = twiddles read from the table (else by products
+ *          of two table loads per radix-16 pass; FP32 butterflies only);
+ *   kind 3 RCMC + azimuth kernel: bit 0 as above for its IFFT, bit 1 = one
+ *          output row per line slot (else two rows sharing their gathers);
+ *   kind 4 batched fused line kernel: bit 0 as above, bits 2-3 = persistent
+ *          grid (0: 2x, 1: 1x, 2: 4x the resident workgroups, 3: one
+ *          workgroup per line group).
+ * The process-wide table starts with every variant 0.  A plan copies the
+ * table's choices for its sizes when it is created (sar_plan, sar_batch_plan);
+ * the first plan of the process loads $SAR_AUTOTUNE_CACHE if that is set.
+ *
+ * The cache is a JSON-lines text file, one flat object per tuned kernel:
+ *   {"arch":"gfx950","kind":"fused","n":4096,"prec":0,"variant":1,
+ *    "us_default":64.1,"us_best":61.9}
+ * (kind names: "fused", "fwd", "inv", "rcmc", "batch_fused").  Lines for
+ * other architectures are preserved; malformed lines are ignored.
+ */
+
+/* Time every candidate variant of the kernels a plan of *p launches (and,
+ * for fused LFM parameters, the batched fused line kernel for Nr and Na) on
+ * the current device, interleaving candidates over five timed rounds of eight
+ * launches and keeping the best; a variant other than 0 wins only if it is at
+ * least 2 % faster.  The winners enter the process-wide table (plans created
+ * afterwards use them) and are merged into the cache at cache_path (NULL:
+ * $SAR_AUTOTUNE_CACHE; neither set: table only).  Allocates two scene-sized
+ * device buffers for the duration; synchronous.
+ * Errors: those of sar_plan; SAR_ERR_NO_MEMORY; SAR_ERR_HIP; SAR_ERR_BAD_PARAM
+ * if the cache cannot be written. */
 sar_status sar_autotune(const sar_params* p, const char* cache_path);
+
+/* Replace the process-wide table by the entries of the cache at path whose
+ * "arch" equals arch (NULL: the current device's gfx name, e.g. "gfx950").
+ * path NULL clears the table.  Host-only when arch is given.  After this call
+ * $SAR_AUTOTUNE_CACHE is no longer read.  Errors: SAR_ERR_BAD_PARAM if path
+ * cannot be read; SAR_ERR_HIP if arch is NULL and there is no device. */
+sar_status sar_tune_load(const char* path, const char* arch);
+
+/* The table's variant for (kind, n, precision): 0 when nothing is tuned,
+ * -1 for an unknown kind.  Host-only. */
+int32_t sar_tune_variant(int32_t kind, int32_t n, int32_t precision);
 
 /* Message for the last non-OK status on the calling thread ("" if none). */
 const char* sar_last_error(void);

@@ -12,14 +12,16 @@ from ._lib import (SarError, make_params, sar_params, sar_plan, sar_plan_destroy
                    sar_azimuth_compress, sar_rda_execute, sar_fft_lines, sar_azimuth_fft,
                    sar_rcmc_azimuth, sar_plan_get_table, sar_batch_plan,
                    sar_batch_workspace_bytes, sar_batch_execute, sar_batch_destroy,
-                   sar_autotune, sar_last_error, sar_version)
+                   sar_autotune, sar_tune_load, sar_tune_variant, sar_last_error,
+                   sar_version)
 
 __all__ = ["Plan", "SarError", "make_params", "sar_params", "sar_plan", "sar_plan_destroy",
            "sar_workspace_bytes", "sar_range_compress", "sar_corner_turn",
            "sar_azimuth_compress", "sar_rda_execute", "sar_fft_lines", "sar_azimuth_fft",
            "sar_rcmc_azimuth", "sar_plan_get_table", "sar_batch_plan",
            "sar_batch_workspace_bytes", "sar_batch_execute", "sar_batch_destroy",
-           "sar_autotune", "sar_last_error", "sar_version"]
+           "sar_autotune", "sar_tune_load", "sar_tune_variant", "sar_last_error",
+           "sar_version"]
 
 
 class Plan:

@@ -26,7 +26,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "sar_rda.h")
 import torch  # noqa: E402,F401
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2604_03585_amd.build` "
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_2604_03585_amd/build.py` "
                       "(the HIP library has no CPU fallback)")
 try:
     _L = ctypes.CDLL(LIB_PATH)
@@ -108,6 +108,9 @@ _sar_batch_execute = _fn("sar_batch_execute", [_vp, ctypes.POINTER(_vp), ctypes.
                                                _vp, _vp])
 _sar_batch_destroy = _fn("sar_batch_destroy", [_vp], None)
 _sar_autotune = _fn("sar_autotune", [_PP, ctypes.c_char_p])
+_sar_tune_load = _fn("sar_tune_load", [ctypes.c_char_p, ctypes.c_char_p])
+_sar_tune_variant = _fn("sar_tune_variant", [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+                        ctypes.c_int32)
 _sar_last_error = _fn("sar_last_error", [], ctypes.c_char_p)
 _sar_version = _fn("sar_version", [], ctypes.c_char_p)
 
@@ -276,3 +279,15 @@ def sar_batch_destroy(batch: int) -> None:
 def sar_autotune(params: sar_params, cache_path: str | None = None):
     _check(_sar_autotune(ctypes.byref(params), cache_path.encode() if cache_path else None),
            "sar_autotune")
+
+
+TUNE_FUSED, TUNE_FWD, TUNE_INV, TUNE_RCMC, TUNE_BATCH_FUSED = range(5)
+
+
+def sar_tune_load(path: str | None, arch: str | None = None):
+    _check(_sar_tune_load(path.encode() if path else None, arch.encode() if arch else None),
+           "sar_tune_load")
+
+
+def sar_tune_variant(kind: int, n: int, precision: int = 0) -> int:
+    return int(_sar_tune_variant(kind, n, precision))

@@ -1,6 +1,6 @@
 """Build libsar_rda.so (HIP, gfx950) in-tree with hipcc.
 
-    python -m paper_2604_03585_amd.build
+    python paper_2604_03585_amd/build.py
 
 Every source under csrc/ is compiled to an object in _build/ (in parallel)
 and the objects are linked into paper_2604_03585_amd/libsar_rda.so.

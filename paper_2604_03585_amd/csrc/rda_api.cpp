@@ -94,6 +94,8 @@ struct sar_plan_s {
     double* rate = nullptr;       // hyperbolic: 2 D / lambda
     float* rcmc_tab = nullptr;    // hyperbolic: interpolation weight coefficients
     double stretch_max = 0.0;     // hyperbolic: 1/D - 1 at |f| = 1/2
+    int var_r[3] = {0, 0, 0};     // tuned variants of the Nr line kernels (fused, fwd, inv)
+    int var_a[4] = {0, 0, 0, 0};  // ... of the Na line kernels (fused, fwd, inv, RCMC)
 };
 
 namespace sar {
@@ -178,18 +180,29 @@ sar::RcmcHost rcmc_host(const sar_plan_s* P)
 
 using sar::LineOp;
 
+}  // namespace
+
+namespace sar {
+RcmcHost plan_rcmc(const sar_plan_s* P) { return rcmc_host(P); }
+}  // namespace sar
+
+namespace {
+
 // ---- steps (no validation; callers validated) ----
 sar_status step_range(const sar_plan_s* P, const void* in, void* out, hipStream_t s)
 {
     const int Nr = P->p.Nr, Na = P->p.Na;
     if (P->p.schedule == SAR_FUSED) {
-        HIP_TRY(sar::launch_line(LineOp::Fused, Nr, in, out, Na, P->Hr, P->tw_r, 1.f, nullptr, P->p.precision, s),
+        HIP_TRY(sar::launch_line(LineOp::Fused, Nr, in, out, Na, P->Hr, P->tw_r, 1.f, nullptr, P->p.precision,
+                                 P->var_r[sar::TK_FUSED], s),
                 "range fused launch");
     } else {
-        HIP_TRY(sar::launch_line(LineOp::Forward, Nr, in, out, Na, nullptr, P->tw_r, 1.f, nullptr, P->p.precision, s),
+        HIP_TRY(sar::launch_line(LineOp::Forward, Nr, in, out, Na, nullptr, P->tw_r, 1.f, nullptr,
+                                 P->p.precision, P->var_r[sar::TK_FWD], s),
                 "range FFT launch");
         HIP_TRY(sar::launch_rowmul(out, out, Na, Nr, P->Hr, s), "range multiply launch");
-        HIP_TRY(sar::launch_line(LineOp::Inverse, Nr, out, out, Na, nullptr, P->tw_r, 1.f, nullptr, P->p.precision, s),
+        HIP_TRY(sar::launch_line(LineOp::Inverse, Nr, out, out, Na, nullptr, P->tw_r, 1.f, nullptr,
+                                 P->p.precision, P->var_r[sar::TK_INV], s),
                 "range IFFT launch");
     }
     return SAR_OK;
@@ -207,27 +220,33 @@ sar_status step_azimuth(const sar_plan_s* P, const void* in, void* out, void* wo
     const int Nr = P->p.Nr, Na = P->p.Na;
     if (P->p.az_model == SAR_AZ_LFM) {
         if (P->p.schedule == SAR_FUSED) {
-            HIP_TRY(sar::launch_line(LineOp::Fused, Na, in, out, Nr, P->Ha, P->tw_a, 1.f, nullptr, P->p.precision, s),
+            HIP_TRY(sar::launch_line(LineOp::Fused, Na, in, out, Nr, P->Ha, P->tw_a, 1.f, nullptr,
+                                     P->p.precision, P->var_a[sar::TK_FUSED], s),
                     "azimuth fused launch");
         } else {
-            HIP_TRY(sar::launch_line(LineOp::Forward, Na, in, out, Nr, nullptr, P->tw_a, 1.f, nullptr, P->p.precision, s),
+            HIP_TRY(sar::launch_line(LineOp::Forward, Na, in, out, Nr, nullptr, P->tw_a, 1.f, nullptr,
+                                     P->p.precision, P->var_a[sar::TK_FWD], s),
                     "azimuth FFT launch");
             HIP_TRY(sar::launch_rowmul(out, out, Nr, Na, P->Ha, s), "azimuth multiply launch");
-            HIP_TRY(sar::launch_line(LineOp::Inverse, Na, out, out, Nr, nullptr, P->tw_a, 1.f, nullptr, P->p.precision, s),
+            HIP_TRY(sar::launch_line(LineOp::Inverse, Na, out, out, Nr, nullptr, P->tw_a, 1.f, nullptr,
+                                     P->p.precision, P->var_a[sar::TK_INV], s),
                     "azimuth IFFT launch");
         }
         return SAR_OK;
     }
     const sar::RcmcHost rh = rcmc_host(P);
-    HIP_TRY(sar::launch_line(LineOp::Forward, Na, in, work, Nr, nullptr, P->tw_a, 1.f, nullptr, P->p.precision, s),
+    HIP_TRY(sar::launch_line(LineOp::Forward, Na, in, work, Nr, nullptr, P->tw_a, 1.f, nullptr,
+                             P->p.precision, P->var_a[sar::TK_FWD], s),
             "azimuth FFT launch");
     if (P->p.schedule == SAR_FUSED) {
-        HIP_TRY(sar::launch_line(LineOp::RcmcAz, Na, work, out, Nr, nullptr, P->tw_a, 1.f, &rh, P->p.precision, s),
+        HIP_TRY(sar::launch_line(LineOp::RcmcAz, Na, work, out, Nr, nullptr, P->tw_a, 1.f, &rh,
+                                 P->p.precision, P->var_a[sar::TK_RCMC], s),
                 "RCMC+azimuth launch");
     } else {
         HIP_TRY(sar::launch_rcmc_interp(work, out, Na, rh, s), "RCMC launch");
         HIP_TRY(sar::launch_az_phase(out, out, Na, rh, 1.0f / (float)Na, s), "azimuth phase launch");
-        HIP_TRY(sar::launch_line(LineOp::Inverse, Na, out, out, Nr, nullptr, P->tw_a, 1.f, nullptr, P->p.precision, s),
+        HIP_TRY(sar::launch_line(LineOp::Inverse, Na, out, out, Nr, nullptr, P->tw_a, 1.f, nullptr,
+                                     P->p.precision, P->var_a[sar::TK_INV], s),
                 "azimuth IFFT launch");
     }
     return SAR_OK;
@@ -239,7 +258,10 @@ extern "C" {
 
 const char* sar_last_error(void) { return g_err.c_str(); }
 
-const char* sar_version(void) { return "sar_rda 0.1 (gfx950, FP32 fused/unfused)"; }
+const char* sar_version(void)
+{
+    return "sar_rda 0.2 (gfx950: FP32 and split FP16/BF16 MFMA, fused/unfused, batched, autotuned)";
+}
 
 sar_status sar_plan(const sar_params* p, void* stream, sar_plan_t* out)
 {
@@ -260,6 +282,9 @@ sar_status sar_plan(const sar_params* p, void* stream, sar_plan_t* out)
     }
     const int Nr = p->Nr, Na = p->Na;
     const bool hyper = p->az_model == SAR_AZ_HYPERBOLIC;
+    sar::load_tune_cache_once();
+    for (int k = 0; k < 3; ++k) P->var_r[k] = sar::tuned_variant(k, Nr, p->precision);
+    for (int k = 0; k < 4; ++k) P->var_a[k] = sar::tuned_variant(k, Na, p->precision);
     const size_t A = 256;
     size_t off = 0;
     const size_t o_twr = off; off = align_up(off + sizeof(float2) * (size_t)sar::twiddle_table_size(Nr), A);
@@ -408,7 +433,8 @@ sar_status sar_fft_lines(sar_plan_t P, int32_t axis, int32_t inverse, const void
     const size_t n = (size_t)lines * N * 8;
     if (in != out && overlap(in, n, out, n)) return fail(SAR_ERR_ALIAS, "in and out partially overlap");
     HIP_TRY(sar::launch_line(inverse ? LineOp::Inverse : LineOp::Forward, N, in, out, lines, nullptr,
-                             axis == 0 ? P->tw_r : P->tw_a, inverse ? 1.0f / (float)N : 1.0f, nullptr, P->p.precision,
+                             axis == 0 ? P->tw_r : P->tw_a, inverse ? 1.0f / (float)N : 1.0f, nullptr,
+                             P->p.precision, (axis == 0 ? P->var_r : P->var_a)[inverse ? sar::TK_INV : sar::TK_FWD],
                              (hipStream_t)stream),
             "FFT launch");
     return SAR_OK;
@@ -435,13 +461,14 @@ sar_status sar_rcmc_azimuth(sar_plan_t P, const void* A, void* out, void* stream
     const sar::RcmcHost rh = rcmc_host(P);
     hipStream_t s = (hipStream_t)stream;
     if (P->p.schedule == SAR_FUSED) {
-        HIP_TRY(sar::launch_line(LineOp::RcmcAz, P->p.Na, A, out, P->p.Nr, nullptr, P->tw_a, 1.f, &rh, P->p.precision, s),
+        HIP_TRY(sar::launch_line(LineOp::RcmcAz, P->p.Na, A, out, P->p.Nr, nullptr, P->tw_a, 1.f, &rh,
+                                 P->p.precision, P->var_a[sar::TK_RCMC], s),
                 "RCMC+azimuth launch");
     } else {
         HIP_TRY(sar::launch_rcmc_interp(A, out, P->p.Na, rh, s), "RCMC launch");
         HIP_TRY(sar::launch_az_phase(out, out, P->p.Na, rh, 1.0f / (float)P->p.Na, s), "phase launch");
         HIP_TRY(sar::launch_line(LineOp::Inverse, P->p.Na, out, out, P->p.Nr, nullptr, P->tw_a, 1.f,
-                                 nullptr, P->p.precision, s),
+                                 nullptr, P->p.precision, P->var_a[sar::TK_INV], s),
                 "azimuth IFFT launch");
     }
     return SAR_OK;

@@ -34,6 +34,7 @@ struct Launch {
     int kind;          // line kind (0 fused)
     int n;             // line length
     int prec;
+    int variant;       // tuned line-kernel variant (line batches)
     size_t task_off;   // byte offset of the task array in the device task buffer
     int ntasks;
     int total;         // groups or tiles
@@ -110,7 +111,9 @@ sar_status build(sar_batch_s* B, const void* const* raw, void* const* img, void*
             groups[{len, B->params[i].precision}].push_back(i);
         }
         for (auto& kv : groups) {
-            Launch L{0, 0, kv.first.first, kv.first.second, host.size(), 0, 0};
+            Launch L{0, 0, kv.first.first, kv.first.second,
+                     sar::tuned_variant(sar::TK_BATCH_FUSED, kv.first.first, kv.first.second),
+                     host.size(), 0, 0};
             for (int i : kv.second) {
                 sar_plan_t P = B->plans[B->plan_of[i]];
                 sar::LineTask t{};
@@ -139,7 +142,7 @@ sar_status build(sar_batch_s* B, const void* const* raw, void* const* img, void*
         }
     };
     auto add_turn_stage = [&](bool back_turn) {
-        Launch L{1, 0, 0, 0, host.size(), 0, 0};
+        Launch L{1, 0, 0, 0, 0, host.size(), 0, 0};
         for (int i = 0; i < n; ++i) {
             if (!batched(B->params[i])) continue;
             const sar_params& p = B->params[i];
@@ -192,7 +195,8 @@ sar_status enqueue(sar_batch_s* B, const void* const* raw, void* const* img, voi
     for (const Launch& L : B->launches) {
         const char* tasks = (const char*)B->dev_tasks + L.task_off;
         hipError_t e = L.type == 0
-                           ? sar::launch_line_batch(L.kind, L.n, tasks, L.ntasks, L.total, 1.0f, L.prec, s)
+                           ? sar::launch_line_batch(L.kind, L.n, tasks, L.ntasks, L.total, 1.0f, L.prec,
+                                                    L.variant, s)
                            : sar::launch_corner_turn_batch(tasks, L.ntasks, L.total, s);
         if (e != hipSuccess) return sar::set_error(SAR_ERR_HIP, "batched launch: %s", hipGetErrorString(e));
     }
@@ -316,16 +320,6 @@ sar_status sar_batch_execute(sar_batch_t B, const void* const* raw, void* const*
         return SAR_OK;
     }
     return enqueue(B, raw, img, work, s);
-}
-
-sar_status sar_autotune(const sar_params* p, const char* cache_path)
-{
-    (void)cache_path;
-    sar_plan_t P = nullptr;
-    sar_status st = sar_plan(p, nullptr, &P);
-    if (st != SAR_OK) return st;
-    sar_plan_destroy(P);
-    return sar::set_error(SAR_ERR_UNSUPPORTED, "autotuning is not built yet");
 }
 
 void sar_batch_destroy(sar_batch_t B)

@@ -56,13 +56,26 @@ struct RcmcHost {
 //  Forward: out = FFT(in) * scale;  Inverse: out = unscaled IFFT(in) * scale
 //  RcmcAz:  out[n] = IFFT(RCMC(in)[n] * phase / n), rh required, lines = rh->nr
 //  prec: 0 FP32 butterflies, 1 split FP16 / 2 split BF16 radix-16 butterflies on MFMA
+//  variant (autotuned): bit 0 twiddles from the table instead of by products,
+//  bit 1 one RCMC output row per line slot instead of two
 hipError_t launch_line(LineOp op, int n, const void* in, void* out, int lines, const void* H,
-                       const void* tw, float scale, const RcmcHost* rh, int prec, hipStream_t s);
+                       const void* tw, float scale, const RcmcHost* rh, int prec, int variant,
+                       hipStream_t s);
 int twiddle_table_size(int n);
 
 // Batched launches (kind: 0 fused, 1 forward, 2 inverse; tasks in device memory).
+//  variant bits 0 (twiddles) and 2-3 (persistent grid: 2x, 1x, 4x resident
+//  workgroups, or one workgroup per line group)
 hipError_t launch_line_batch(int kind, int n, const void* tasks, int ntasks, int total_groups,
-                             float scale, int prec, hipStream_t s);
+                             float scale, int prec, int variant, hipStream_t s);
+
+// Autotuned kernel variants, per (kernel kind, line length, precision).  The
+// table starts empty (every variant 0) and is filled by sar_autotune or from a
+// JSON-lines cache named by SAR_AUTOTUNE_CACHE when the first plan is built.
+enum TuneKind { TK_FUSED = 0, TK_FWD = 1, TK_INV = 2, TK_RCMC = 3, TK_BATCH_FUSED = 4 };
+int tuned_variant(int kind, int n, int prec);
+void load_tune_cache_once();
+
 hipError_t launch_corner_turn_batch(const void* tasks, int ntasks, int total_tiles, hipStream_t s);
 int line_groups(int n, int lines);        // line groups of `lines` lines of length n
 
@@ -74,6 +87,7 @@ struct PlanTables {
     const void* tw_a;
 };
 PlanTables plan_tables(const sar_plan_s* P);
+RcmcHost plan_rcmc(const sar_plan_s* P);   // hyperbolic plans only
 int turn_tiles(int rows, int cols);       // 64 x 64 tiles of a corner turn
 
 hipError_t launch_rowmul(const void* in, void* out, int rows, int n, const void* H, hipStream_t s);

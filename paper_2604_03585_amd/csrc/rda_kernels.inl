@@ -118,13 +118,13 @@ template <int N> struct LineLaunch {
 
 // Line transform in the requested butterfly precision: FP32 VALU passes, or
 // split FP16 / BF16 radix-16 passes on MFMA (twiddles and filters in FP32).
-template <int N, bool INV, int PREC, class F = NoOp>
+template <int N, bool INV, int PREC, bool TWP = true, class F = NoOp>
 __device__ __forceinline__ void fft_any(float2 (&x)[line_e(N)], float2* __restrict__ lds,
                                         const float2* __restrict__ tw, int sub, int t,
                                         F&& before_last = F())
 {
     if constexpr (PREC == PREC_FP32) {
-        fft_line<N, INV>(x, lds, tw, t, before_last);
+        fft_line<N, INV, TWP>(x, lds, tw, t, before_last);
     } else {
         using L = LineLaunch<N>;
         before_last();
@@ -162,8 +162,10 @@ enum LineKind { LK_FUSED = 0, LK_FWD = 1, LK_INV = 2 };
 
 //  LK_FUSED: out = IFFT(FFT(in) * H)      (H carries the 1/N)
 //  LK_FWD:   out = FFT(in) * scale;  LK_INV: out = IFFT_unscaled(in) * scale
-// One group of LPW lines starting at line g * LPW of `in` / `out`.
-template <int N, int KIND, int PREC>
+// One group of LPW lines starting at line g * LPW of `in` / `out`.  TWP:
+// twiddles by products (true) or straight table reads (false), chosen per
+// line length by the autotuner.
+template <int N, int KIND, int PREC, bool TWP>
 __device__ __forceinline__ void line_group(const float2* in, float2* out, int lines,
                                            const float2* __restrict__ H,
                                            const float2* __restrict__ tw, float scale, int g,
@@ -184,15 +186,15 @@ __device__ __forceinline__ void line_group(const float2* in, float2* out, int li
     if constexpr (KIND == LK_FUSED) {
         // the filter is requested just before the last forward pass
         float2 h[E];
-        fft_any<N, false, PREC>(x, lds, tw, sub, t, [&] {
+        fft_any<N, false, PREC, TWP>(x, lds, tw, sub, t, [&] {
 #pragma unroll
             for (int m = 0; m < E; ++m) h[m] = H[t + m * L::T];
         });
 #pragma unroll
         for (int m = 0; m < E; ++m) x[m] = c_mul(x[m], h[m]);
-        fft_any<N, true, PREC>(x, lds, tw, sub, t);
+        fft_any<N, true, PREC, TWP>(x, lds, tw, sub, t);
     } else {
-        fft_any<N, KIND == LK_INV, PREC>(x, lds, tw, sub, t);
+        fft_any<N, KIND == LK_INV, PREC, TWP>(x, lds, tw, sub, t);
         if (scale != 1.0f) {
 #pragma unroll
             for (int m = 0; m < E; ++m) x[m] = c_scale(x[m], scale);
@@ -201,20 +203,20 @@ __device__ __forceinline__ void line_group(const float2* in, float2* out, int li
     if (live) store_line<N>(x, out + (size_t)line * N, t);
 }
 
-template <int N, int KIND, int PREC>
+template <int N, int KIND, int PREC, bool TWP>
 __global__ __launch_bounds__(LineLaunch<N>::BLOCK) void
 k_line(const float2* in, float2* out, int lines, const float2* __restrict__ H,
        const float2* __restrict__ tw, float scale)
 {
     extern __shared__ float2 smem[];
-    line_group<N, KIND, PREC>(in, out, lines, H, tw, scale, blockIdx.x, smem);
+    line_group<N, KIND, PREC, TWP>(in, out, lines, H, tw, scale, blockIdx.x, smem);
 }
 
 // Batched form: the line groups of many scenes (tasks) in one launch.  The
 // grid covers min(total groups, resident capacity) workgroups, each walking
 // groups gg = blockIdx.x, + gridDim.x, ...; the task of a group is found by
 // binary search over the tasks' first-group indices (sorted).
-template <int N, int KIND, int PREC>
+template <int N, int KIND, int PREC, bool TWP>
 __global__ __launch_bounds__(LineLaunch<N>::BLOCK) void
 k_line_batch(const LineTask* __restrict__ tasks, int ntasks, int total_groups, float scale)
 {
@@ -227,8 +229,8 @@ k_line_batch(const LineTask* __restrict__ tasks, int ntasks, int total_groups, f
             else hi = mid - 1;
         }
         const LineTask tk = tasks[lo];
-        line_group<N, KIND, PREC>(tk.in, tk.out, tk.lines, tk.H, tk.tw, scale,
-                                  gg - tk.group_begin, smem);
+        line_group<N, KIND, PREC, TWP>(tk.in, tk.out, tk.lines, tk.H, tk.tw, scale,
+                                       gg - tk.group_begin, smem);
         __syncthreads();                          // LDS reuse by the next group
     }
 }
@@ -822,12 +824,20 @@ static hipError_t set_lds_limit()
 {
     using L = LineLaunch<N>;
     if (L::LDS_BYTES <= 64 * 1024) return hipSuccess;
-    const void* fns[] = {(const void*)k_line<N, LK_FUSED, PREC>, (const void*)k_line<N, LK_FWD, PREC>,
-                         (const void*)k_line<N, LK_INV, PREC>, (const void*)k_rcmc_az<N, 0, PREC>,
-                         (const void*)k_rcmc_az<N, 8, PREC>, (const void*)k_rcmc_az2<N, PREC>,
-                         (const void*)k_line_batch<N, LK_FUSED, PREC>,
-                         (const void*)k_line_batch<N, LK_FWD, PREC>,
-                         (const void*)k_line_batch<N, LK_INV, PREC>};
+    const void* fns[] = {(const void*)k_line<N, LK_FUSED, PREC, true>,
+                         (const void*)k_line<N, LK_FWD, PREC, true>,
+                         (const void*)k_line<N, LK_INV, PREC, true>,
+                         (const void*)k_line<N, LK_FUSED, PREC, false>,
+                         (const void*)k_line<N, LK_FWD, PREC, false>,
+                         (const void*)k_line<N, LK_INV, PREC, false>,
+                         (const void*)k_rcmc_az<N, 0, PREC>, (const void*)k_rcmc_az<N, 8, PREC>,
+                         (const void*)k_rcmc_az2<N, PREC>,
+                         (const void*)k_line_batch<N, LK_FUSED, PREC, true>,
+                         (const void*)k_line_batch<N, LK_FWD, PREC, true>,
+                         (const void*)k_line_batch<N, LK_INV, PREC, true>,
+                         (const void*)k_line_batch<N, LK_FUSED, PREC, false>,
+                         (const void*)k_line_batch<N, LK_FWD, PREC, false>,
+                         (const void*)k_line_batch<N, LK_INV, PREC, false>};
     for (const void* f : fns) {
         const hipError_t e =
             hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, L::LDS_BYTES);
@@ -838,33 +848,42 @@ static hipError_t set_lds_limit()
 
 template <int N, int KIND, int PREC>
 static hipError_t launch_k_line(const float2* in, float2* out, int lines, const float2* H,
-                                const float2* tw, float scale, hipStream_t s)
+                                const float2* tw, float scale, int variant, hipStream_t s)
 {
     using L = LineLaunch<N>;
     const int groups = (lines + L::LPW - 1) / L::LPW;
     if (groups == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_line<N, KIND, PREC>), dim3(groups), dim3(L::BLOCK), L::LDS_BYTES, s, in,
-                       out, lines, H, tw, scale);
+    // variant bit 0: twiddles from the table (FP32 butterflies only)
+    if (PREC == PREC_FP32 && (variant & 1))
+        hipLaunchKernelGGL((k_line<N, KIND, PREC, false>), dim3(groups), dim3(L::BLOCK),
+                           L::LDS_BYTES, s, in, out, lines, H, tw, scale);
+    else
+        hipLaunchKernelGGL((k_line<N, KIND, PREC, true>), dim3(groups), dim3(L::BLOCK),
+                           L::LDS_BYTES, s, in, out, lines, H, tw, scale);
     return hipGetLastError();
 }
 
 template <int N, int PREC>
 static hipError_t launch_line_n(LineOp op, const float2* in, float2* out, int lines,
                                 const float2* H, const float2* tw, float scale,
-                                const RcmcArgs* ra, int taps, hipStream_t s)
+                                const RcmcArgs* ra, int taps, int variant, hipStream_t s)
 {
     using L = LineLaunch<N>;
     static const hipError_t attr = set_lds_limit<N, PREC>();
     if (attr != hipSuccess) return attr;
     switch (op) {
-    case LineOp::Fused: return launch_k_line<N, LK_FUSED, PREC>(in, out, lines, H, tw, 1.0f, s);
-    case LineOp::Forward: return launch_k_line<N, LK_FWD, PREC>(in, out, lines, nullptr, tw, scale, s);
-    case LineOp::Inverse: return launch_k_line<N, LK_INV, PREC>(in, out, lines, nullptr, tw, scale, s);
+    case LineOp::Fused:
+        return launch_k_line<N, LK_FUSED, PREC>(in, out, lines, H, tw, 1.0f, variant, s);
+    case LineOp::Forward:
+        return launch_k_line<N, LK_FWD, PREC>(in, out, lines, nullptr, tw, scale, variant, s);
+    case LineOp::Inverse:
+        return launch_k_line<N, LK_INV, PREC>(in, out, lines, nullptr, tw, scale, variant, s);
     case LineOp::RcmcAz: {
         const int groups = (lines + L::LPW - 1) / L::LPW;
         if (groups == 0) return hipSuccess;
         static_assert(L::LDS_BYTES >= RCMC_TAB * (int)sizeof(float), "table fits the line LDS");
-        if (taps == 8 && ra->stretch_max < 0.5 && (lines & 1) == 0) {
+        // variant bit 1: one output row per line slot instead of two
+        if (taps == 8 && ra->stretch_max < 0.5 && (lines & 1) == 0 && !(variant & 2)) {
             const int g2 = (lines / 2 + L::LPW - 1) / L::LPW;
             hipLaunchKernelGGL((k_rcmc_az2<N, PREC>), dim3(g2), dim3(L::BLOCK), L::LDS_BYTES, s, in,
                                out, *ra, tw);
@@ -880,49 +899,65 @@ static hipError_t launch_line_n(LineOp op, const float2* in, float2* out, int li
     return hipErrorInvalidValue;
 }
 
-template <int N, int PREC>
-static hipError_t launch_line_batch_n(int kind, const LineTask* tasks, int ntasks, int total_groups,
-                                      float scale, hipStream_t s)
+template <int N, int PREC, bool TWP>
+static hipError_t launch_line_batch_t(int kind, const LineTask* tasks, int ntasks, int total_groups,
+                                      float scale, int grid_sel, hipStream_t s)
 {
     using L = LineLaunch<N>;
     static const hipError_t attr = set_lds_limit<N, PREC>();
     if (attr != hipSuccess) return attr;
     if (total_groups == 0) return hipSuccess;
-    // resident capacity: LDS-limited workgroups per CU x 256 CUs
+    // Persistent grid: a multiple of the resident capacity (LDS-limited
+    // workgroups per CU x 256 CUs); grid_sel 0: 2x, 1: 1x, 2: 4x, 3: one
+    // workgroup per line group (not persistent).
     const int per_cu = (160 * 1024) / L::LDS_BYTES;
-    const int cap = (per_cu < 1 ? 1 : per_cu) * 256 * 2;
+    const int resident = (per_cu < 1 ? 1 : per_cu) * 256;
+    const int mult[4] = {2, 1, 4, 0};
+    const int cap = mult[grid_sel & 3] ? resident * mult[grid_sel & 3] : total_groups;
     const int grid = total_groups < cap ? total_groups : cap;
     switch (kind) {
     case LK_FUSED:
-        hipLaunchKernelGGL((k_line_batch<N, LK_FUSED, PREC>), dim3(grid), dim3(L::BLOCK),
+        hipLaunchKernelGGL((k_line_batch<N, LK_FUSED, PREC, TWP>), dim3(grid), dim3(L::BLOCK),
                            L::LDS_BYTES, s, tasks, ntasks, total_groups, scale);
         break;
     case LK_FWD:
-        hipLaunchKernelGGL((k_line_batch<N, LK_FWD, PREC>), dim3(grid), dim3(L::BLOCK),
+        hipLaunchKernelGGL((k_line_batch<N, LK_FWD, PREC, TWP>), dim3(grid), dim3(L::BLOCK),
                            L::LDS_BYTES, s, tasks, ntasks, total_groups, scale);
         break;
     default:
-        hipLaunchKernelGGL((k_line_batch<N, LK_INV, PREC>), dim3(grid), dim3(L::BLOCK),
+        hipLaunchKernelGGL((k_line_batch<N, LK_INV, PREC, TWP>), dim3(grid), dim3(L::BLOCK),
                            L::LDS_BYTES, s, tasks, ntasks, total_groups, scale);
         break;
     }
     return hipGetLastError();
 }
 
+template <int N, int PREC>
+static hipError_t launch_line_batch_n(int kind, const LineTask* tasks, int ntasks, int total_groups,
+                                      float scale, int variant, hipStream_t s)
+{
+    // variant bit 0: table twiddles (FP32); bits 2-3: persistent grid size
+    const int grid_sel = (variant >> 2) & 3;
+    if (PREC == PREC_FP32 && (variant & 1))
+        return launch_line_batch_t<N, PREC, false>(kind, tasks, ntasks, total_groups, scale,
+                                                   grid_sel, s);
+    return launch_line_batch_t<N, PREC, true>(kind, tasks, ntasks, total_groups, scale, grid_sel, s);
+}
+
 template <int PREC>
 static hipError_t launch_line_batch_prec(int kind, int n, const LineTask* tasks, int ntasks,
-                                         int total_groups, float scale, hipStream_t s)
+                                         int total_groups, float scale, int v, hipStream_t s)
 {
     switch (n) {
-    case 64: return launch_line_batch_n<64, PREC>(kind, tasks, ntasks, total_groups, scale, s);
-    case 128: return launch_line_batch_n<128, PREC>(kind, tasks, ntasks, total_groups, scale, s);
-    case 256: return launch_line_batch_n<256, PREC>(kind, tasks, ntasks, total_groups, scale, s);
-    case 512: return launch_line_batch_n<512, PREC>(kind, tasks, ntasks, total_groups, scale, s);
-    case 1024: return launch_line_batch_n<1024, PREC>(kind, tasks, ntasks, total_groups, scale, s);
-    case 2048: return launch_line_batch_n<2048, PREC>(kind, tasks, ntasks, total_groups, scale, s);
-    case 4096: return launch_line_batch_n<4096, PREC>(kind, tasks, ntasks, total_groups, scale, s);
-    case 8192: return launch_line_batch_n<8192, PREC>(kind, tasks, ntasks, total_groups, scale, s);
-    case 16384: return launch_line_batch_n<16384, PREC>(kind, tasks, ntasks, total_groups, scale, s);
+    case 64: return launch_line_batch_n<64, PREC>(kind, tasks, ntasks, total_groups, scale, v, s);
+    case 128: return launch_line_batch_n<128, PREC>(kind, tasks, ntasks, total_groups, scale, v, s);
+    case 256: return launch_line_batch_n<256, PREC>(kind, tasks, ntasks, total_groups, scale, v, s);
+    case 512: return launch_line_batch_n<512, PREC>(kind, tasks, ntasks, total_groups, scale, v, s);
+    case 1024: return launch_line_batch_n<1024, PREC>(kind, tasks, ntasks, total_groups, scale, v, s);
+    case 2048: return launch_line_batch_n<2048, PREC>(kind, tasks, ntasks, total_groups, scale, v, s);
+    case 4096: return launch_line_batch_n<4096, PREC>(kind, tasks, ntasks, total_groups, scale, v, s);
+    case 8192: return launch_line_batch_n<8192, PREC>(kind, tasks, ntasks, total_groups, scale, v, s);
+    case 16384: return launch_line_batch_n<16384, PREC>(kind, tasks, ntasks, total_groups, scale, v, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -930,68 +965,69 @@ static hipError_t launch_line_batch_prec(int kind, int n, const LineTask* tasks,
 template <int PREC>
 static hipError_t launch_line_prec(LineOp op, int n, const float2* i, float2* o, int lines,
                                    const float2* h, const float2* w, float scale,
-                                   const RcmcArgs* ra, int taps, hipStream_t s)
+                                   const RcmcArgs* ra, int taps, int v, hipStream_t s)
 {
     switch (n) {
-    case 64: return launch_line_n<64, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
-    case 128: return launch_line_n<128, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
-    case 256: return launch_line_n<256, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
-    case 512: return launch_line_n<512, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
-    case 1024: return launch_line_n<1024, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
-    case 2048: return launch_line_n<2048, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
-    case 4096: return launch_line_n<4096, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
-    case 8192: return launch_line_n<8192, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
-    case 16384: return launch_line_n<16384, PREC>(op, i, o, lines, h, w, scale, ra, taps, s);
+    case 64: return launch_line_n<64, PREC>(op, i, o, lines, h, w, scale, ra, taps, v, s);
+    case 128: return launch_line_n<128, PREC>(op, i, o, lines, h, w, scale, ra, taps, v, s);
+    case 256: return launch_line_n<256, PREC>(op, i, o, lines, h, w, scale, ra, taps, v, s);
+    case 512: return launch_line_n<512, PREC>(op, i, o, lines, h, w, scale, ra, taps, v, s);
+    case 1024: return launch_line_n<1024, PREC>(op, i, o, lines, h, w, scale, ra, taps, v, s);
+    case 2048: return launch_line_n<2048, PREC>(op, i, o, lines, h, w, scale, ra, taps, v, s);
+    case 4096: return launch_line_n<4096, PREC>(op, i, o, lines, h, w, scale, ra, taps, v, s);
+    case 8192: return launch_line_n<8192, PREC>(op, i, o, lines, h, w, scale, ra, taps, v, s);
+    case 16384: return launch_line_n<16384, PREC>(op, i, o, lines, h, w, scale, ra, taps, v, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 // One instantiation of launch_line_prec / launch_line_batch_prec per part
 // (defined in parts 1-3).
-hipError_t launch_line_batch_p1(int, int, const LineTask*, int, int, float, hipStream_t);
-hipError_t launch_line_batch_p2(int, int, const LineTask*, int, int, float, hipStream_t);
-hipError_t launch_line_batch_p3(int, int, const LineTask*, int, int, float, hipStream_t);
+hipError_t launch_line_batch_p1(int, int, const LineTask*, int, int, float, int, hipStream_t);
+hipError_t launch_line_batch_p2(int, int, const LineTask*, int, int, float, int, hipStream_t);
+hipError_t launch_line_batch_p3(int, int, const LineTask*, int, int, float, int, hipStream_t);
 hipError_t launch_line_fp32(LineOp, int, const float2*, float2*, int, const float2*, const float2*,
-                            float, const RcmcArgs*, int, hipStream_t);
+                            float, const RcmcArgs*, int, int, hipStream_t);
 hipError_t launch_line_f16(LineOp, int, const float2*, float2*, int, const float2*, const float2*,
-                           float, const RcmcArgs*, int, hipStream_t);
+                           float, const RcmcArgs*, int, int, hipStream_t);
 hipError_t launch_line_bf16(LineOp, int, const float2*, float2*, int, const float2*, const float2*,
-                            float, const RcmcArgs*, int, hipStream_t);
+                            float, const RcmcArgs*, int, int, hipStream_t);
 
 #if SAR_PART >= 1
 hipError_t SAR_LINE_BATCH_FN(int kind, int n, const LineTask* tasks, int ntasks, int total_groups,
-                             float scale, hipStream_t s)
+                             float scale, int v, hipStream_t s)
 {
-    return launch_line_batch_prec<SAR_PART - 1>(kind, n, tasks, ntasks, total_groups, scale, s);
+    return launch_line_batch_prec<SAR_PART - 1>(kind, n, tasks, ntasks, total_groups, scale, v, s);
 }
 #endif
 
 #if SAR_PART == 1
 hipError_t launch_line_fp32(LineOp op, int n, const float2* i, float2* o, int lines,
                             const float2* h, const float2* w, float scale, const RcmcArgs* ra,
-                            int taps, hipStream_t s)
+                            int taps, int v, hipStream_t s)
 {
-    return launch_line_prec<PREC_FP32>(op, n, i, o, lines, h, w, scale, ra, taps, s);
+    return launch_line_prec<PREC_FP32>(op, n, i, o, lines, h, w, scale, ra, taps, v, s);
 }
 #elif SAR_PART == 2
 hipError_t launch_line_f16(LineOp op, int n, const float2* i, float2* o, int lines,
                            const float2* h, const float2* w, float scale, const RcmcArgs* ra,
-                           int taps, hipStream_t s)
+                           int taps, int v, hipStream_t s)
 {
-    return launch_line_prec<PREC_F16>(op, n, i, o, lines, h, w, scale, ra, taps, s);
+    return launch_line_prec<PREC_F16>(op, n, i, o, lines, h, w, scale, ra, taps, v, s);
 }
 #elif SAR_PART == 3
 hipError_t launch_line_bf16(LineOp op, int n, const float2* i, float2* o, int lines,
                             const float2* h, const float2* w, float scale, const RcmcArgs* ra,
-                            int taps, hipStream_t s)
+                            int taps, int v, hipStream_t s)
 {
-    return launch_line_prec<PREC_BF16>(op, n, i, o, lines, h, w, scale, ra, taps, s);
+    return launch_line_prec<PREC_BF16>(op, n, i, o, lines, h, w, scale, ra, taps, v, s);
 }
 #endif
 
 #if SAR_PART == 0
 hipError_t launch_line(LineOp op, int n, const void* in, void* out, int lines, const void* H,
-                       const void* tw, float scale, const RcmcHost* rh, int prec, hipStream_t s)
+                       const void* tw, float scale, const RcmcHost* rh, int prec, int variant,
+                       hipStream_t s)
 {
     RcmcArgs ra{};
     int taps = 0;
@@ -1004,21 +1040,21 @@ hipError_t launch_line(LineOp op, int n, const void* in, void* out, int lines, c
     auto h = (const float2*)H;
     auto w = (const float2*)tw;
     switch (prec) {
-    case PREC_FP32: return launch_line_fp32(op, n, i, o, lines, h, w, scale, &ra, taps, s);
-    case PREC_F16: return launch_line_f16(op, n, i, o, lines, h, w, scale, &ra, taps, s);
-    case PREC_BF16: return launch_line_bf16(op, n, i, o, lines, h, w, scale, &ra, taps, s);
+    case PREC_FP32: return launch_line_fp32(op, n, i, o, lines, h, w, scale, &ra, taps, variant, s);
+    case PREC_F16: return launch_line_f16(op, n, i, o, lines, h, w, scale, &ra, taps, variant, s);
+    case PREC_BF16: return launch_line_bf16(op, n, i, o, lines, h, w, scale, &ra, taps, variant, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_line_batch(int kind, int n, const void* tasks, int ntasks, int total_groups,
-                             float scale, int prec, hipStream_t s)
+                             float scale, int prec, int variant, hipStream_t s)
 {
     const LineTask* t = (const LineTask*)tasks;
     switch (prec) {
-    case PREC_FP32: return launch_line_batch_p1(kind, n, t, ntasks, total_groups, scale, s);
-    case PREC_F16: return launch_line_batch_p2(kind, n, t, ntasks, total_groups, scale, s);
-    case PREC_BF16: return launch_line_batch_p3(kind, n, t, ntasks, total_groups, scale, s);
+    case PREC_FP32: return launch_line_batch_p1(kind, n, t, ntasks, total_groups, scale, variant, s);
+    case PREC_F16: return launch_line_batch_p2(kind, n, t, ntasks, total_groups, scale, variant, s);
+    case PREC_BF16: return launch_line_batch_p3(kind, n, t, ntasks, total_groups, scale, variant, s);
     default: return hipErrorInvalidValue;
     }
 }

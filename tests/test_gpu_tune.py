@@ -1,0 +1,131 @@
+"""The autotuner on the device: sar_autotune writes a cache the next plans
+use, and every kernel variant it can choose gives the oracle's result
+(variants differ in scheduling only: relative L2 <= 1e-5 against the FP64
+oracle, <= 1e-6 against the default variant; batched = single-scene
+bit-identical when both use the same twiddle scheme)."""
+import json
+
+import numpy as np
+import pytest
+
+import paper_2604_03585_amd as sar
+from gpu_util import dev, host, rel_l2, torch_cuda
+from oracle import oracle as O
+from paper_2604_03585_amd import _lib
+from sarsim import batch_configs, config, simulate
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["fused", "fwd", "inv", "rcmc", "batch_fused"]
+
+
+def arch():
+    torch = torch_cuda()
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def write_cache(path, entries):
+    a = arch()
+    with open(path, "w") as f:
+        for kind, n, prec, v in entries:
+            f.write(json.dumps({"arch": a, "kind": kind, "n": n, "prec": prec, "variant": v}) + "\n")
+    sar.sar_tune_load(str(path))
+
+
+@pytest.fixture(autouse=True)
+def clear_table():
+    yield
+    sar.sar_tune_load(None)
+
+
+_oracle = {}
+
+
+def scene(name, **over):
+    key = (name, tuple(sorted(over.items())))
+    if key not in _oracle:
+        cfg = config(name, **over)
+        sc = simulate(cfg)
+        _oracle[key] = (cfg, sc, O.rda(sc.raw, cfg))
+    return _oracle[key]
+
+
+def run(cfg, raw, **opts):
+    with sar.Plan(cfg, **opts) as p:
+        return host(p.execute(dev(raw))).T
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_autotune_writes_cache_and_plans_use_it(tmp_path, name):
+    cfg, sc, ref = scene(name)
+    path = tmp_path / "tune.jsonl"
+    sar.sar_autotune(sar.make_params(cfg), str(path))
+    lines = [json.loads(l) for l in path.read_text().splitlines()]
+    kinds = {(e["kind"], e["n"]) for e in lines}
+    if cfg["az_model"] == "lfm":
+        want = {("fused", cfg["Nr"]), ("fused", cfg["Na"]), ("batch_fused", cfg["Nr"]),
+                ("batch_fused", cfg["Na"])}
+    else:
+        want = {("fused", cfg["Nr"]), ("fwd", cfg["Na"]), ("rcmc", cfg["Na"])}
+    assert kinds == want
+    for e in lines:
+        assert e["arch"] == arch()
+        assert e["us_best"] <= e["us_default"]
+        assert sar.sar_tune_variant(KINDS.index(e["kind"]), e["n"], 0) == e["variant"]
+        print(e)
+    # tuning again merges (same keys replaced, not duplicated)
+    sar.sar_autotune(sar.make_params(cfg), str(path))
+    assert len(path.read_text().splitlines()) == len(lines)
+    img = run(cfg, sc.raw)
+    assert rel_l2(img, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("rcmc_variant", [0, 1, 2, 3])
+def test_hyperbolic_variants_match_oracle(tmp_path, rcmc_variant):
+    cfg, sc, ref = scene("c2")
+    base = run(cfg, sc.raw)
+    tw = rcmc_variant & 1
+    write_cache(tmp_path / "t.jsonl", [("fused", cfg["Nr"], 0, tw), ("fwd", cfg["Na"], 0, tw),
+                                       ("rcmc", cfg["Na"], 0, rcmc_variant)])
+    assert sar.sar_tune_variant(_lib.TUNE_RCMC, cfg["Na"], 0) == rcmc_variant
+    img = run(cfg, sc.raw)
+    e_ref, e_base = rel_l2(img, ref), rel_l2(img, base)
+    print(f"RCMC variant {rcmc_variant}: vs oracle {e_ref:.3e}, vs default {e_base:.3e}")
+    assert e_ref <= 1e-5 and e_base <= 1e-6
+
+
+@pytest.mark.parametrize("schedule", ["fused", "unfused"])
+def test_lfm_table_twiddles_match_oracle(tmp_path, schedule):
+    cfg, sc, ref = scene("c1")
+    base = run(cfg, sc.raw, schedule=schedule)
+    n = cfg["Nr"]
+    write_cache(tmp_path / "t.jsonl", [(k, n, 0, 1) for k in ("fused", "fwd", "inv")])
+    img = run(cfg, sc.raw, schedule=schedule)
+    assert rel_l2(img, ref) <= 1e-5 and rel_l2(img, base) <= 1e-6
+
+
+@pytest.mark.parametrize("variant", [0, 1, 4, 5, 8, 9, 12, 13])
+def test_batch_variants_bit_identical_to_single(tmp_path, variant):
+    torch = torch_cuda()
+    cfgs = batch_configs(seed=4, n=64, nr_choices=(256, 512, 1024), na_choices=(256, 512))[:5]
+    sizes = sorted({c["Nr"] for c in cfgs} | {c["Na"] for c in cfgs})
+    write_cache(tmp_path / "t.jsonl", [("fused", n, 0, variant & 1) for n in sizes] +
+                [("batch_fused", n, 0, variant) for n in sizes])
+    scenes = [simulate(c) for c in cfgs]
+    params = [sar.make_params(c) for c in cfgs]
+    stream = torch.cuda.Stream()
+    b = sar.sar_batch_plan(params, stream)
+    try:
+        raws = [dev(s.raw) for s in scenes]
+        imgs = [torch.empty(s.raw.shape[::-1], dtype=torch.complex64, device="cuda")
+                for s in scenes]
+        work = torch.empty(sar.sar_batch_workspace_bytes(b) // 8 + 1, dtype=torch.complex64,
+                           device="cuda")
+        for _ in range(2):
+            sar.sar_batch_execute(b, raws, imgs, work, stream)
+        stream.synchronize()
+        for c, s, img in zip(cfgs, scenes, imgs):
+            single = run(c, s.raw)
+            assert np.array_equal(host(img).T, single)
+    finally:
+        sar.sar_batch_destroy(b)
