@@ -20,7 +20,7 @@
  *                compression (multiply by H_a(f_a, R0), then IFFT).
  * The paper defines neither filter nor the RCMC kernel; the readings used
  * here (replica matched filters, exact-geometry azimuth phase, 8-tap
- * Kaiser-windowed sinc) are the ones listed in the design notes.
+ * Kaiser-windowed sinc) are stated at each function below.
  *
  * Parity status of each function is stated in its comment; every one is
  * pinned by a CPU test against a closed form, brute force, or an invariant.

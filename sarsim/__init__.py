@@ -6,8 +6,9 @@ nothing of the Range Doppler Algorithm itself: no FFT, no matched filter, no
 RCMC.  Both sides receive the same complex64 array and the same parameter
 dictionary.
 """
-from .configs import CONFIGS, config, batch_configs, serve_pool_configs
-from .scene import Scene, simulate
+from .configs import (CONFIGS, config, batch_configs, lfm_scene, poisson_arrivals,
+                      serve_pool_configs)
+from .scene import Scene, simulate, simulate_many
 
-__all__ = ["CONFIGS", "config", "batch_configs", "serve_pool_configs",
-           "Scene", "simulate"]
+__all__ = ["CONFIGS", "config", "batch_configs", "lfm_scene", "poisson_arrivals",
+           "serve_pool_configs", "Scene", "simulate", "simulate_many"]

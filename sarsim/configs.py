@@ -4,7 +4,7 @@ The paper measures a private 4096 x 4096 complex float32 point-target
 simulation with 5 targets and 20 dB additive Gaussian noise (Sec. V.A).  The
 simulator and its parameters are not published, so the dictionaries below are
 our stand-ins; every value that the paper leaves open carries the reading we
-took for it (the same readings are listed in the design notes).
+took for it.
 
 A scene dictionary carries two kinds of keys:
 
@@ -64,7 +64,7 @@ def config(name: str, **overrides) -> dict:
     return d
 
 
-def _lfm_scene(Nr: int, Na: int, n_targets: int, seed: int, name: str) -> dict:
+def lfm_scene(Nr: int, Na: int, n_targets: int, seed: int, name: str) -> dict:
     """An LFM-azimuth scene whose chirps span 1/8 of each dimension, TBP = L/2."""
     Lr, La = Nr // 8, Na // 8
     return dict(
@@ -91,7 +91,7 @@ def batch_configs(seed: int = 4, n: int = 64,
     na = rng.choice(np.asarray(na_choices), size=n)
     nt = rng.integers(3, 10, size=n)
     seeds = rng.integers(0, 2**63 - 1, size=n, dtype=np.int64)
-    return [_lfm_scene(int(nr[i]), int(na[i]), int(nt[i]), int(seeds[i]),
+    return [lfm_scene(int(nr[i]), int(na[i]), int(nt[i]), int(seeds[i]),
                        f"batch{i:02d}_{int(na[i])}x{int(nr[i])}")
             for i in range(n)]
 
@@ -104,7 +104,7 @@ def serve_pool_configs(seed: int = 5, n: int = 32,
     nr = rng.choice(np.asarray(nr_choices), size=n)
     na = rng.choice(np.asarray(na_choices), size=n)
     seeds = rng.integers(0, 2**63 - 1, size=n, dtype=np.int64)
-    return [_lfm_scene(int(nr[i]), int(na[i]), 5, int(seeds[i]),
+    return [lfm_scene(int(nr[i]), int(na[i]), 5, int(seeds[i]),
                        f"pool{i:02d}_{int(na[i])}x{int(nr[i])}")
             for i in range(n)]
 

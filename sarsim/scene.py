@@ -131,3 +131,26 @@ def simulate(cfg: dict, noise: bool = True, targets=None) -> Scene:
         raw[rs, cs] = acc.astype(np.complex64)
 
     return Scene(params=dict(cfg), raw=np.ascontiguousarray(raw), targets=tlist)
+
+
+def simulate_many(cfgs, workers: int = 8, consume=None):
+    """simulate() for many scenes on a thread pool (numpy's generators and
+    array arithmetic release the GIL).  Each scene draws from its own seeded
+    stream, so the result does not depend on ``workers``.  With ``consume``,
+    each scene is passed to consume(index, scene) in order and not kept (at
+    most 2 x workers scenes are held at once); else the list is returned."""
+    import concurrent.futures as cf
+    cfgs = list(cfgs)
+    out = []
+    window = 2 * max(1, workers)
+    with cf.ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        futs = {i: ex.submit(simulate, cfgs[i]) for i in range(min(window, len(cfgs)))}
+        for i in range(len(cfgs)):
+            sc = futs.pop(i).result()
+            if i + window < len(cfgs):
+                futs[i + window] = ex.submit(simulate, cfgs[i + window])
+            if consume is None:
+                out.append(sc)
+            else:
+                consume(i, sc)
+    return out if consume is None else None
