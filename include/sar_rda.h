@@ -203,9 +203,9 @@ void sar_batch_destroy(sar_batch_t batch);
  *          of two table loads per radix-16 pass; FP32 butterflies only);
  *   kind 3 RCMC + azimuth kernel: bit 0 as above for its IFFT, bit 1 = one
  *          output row per line slot (else two rows sharing their gathers);
- *   kind 4 batched fused line kernel: bit 0 as above, bits 2-3 = persistent
- *          grid (0: 2x, 1: 1x, 2: 4x the resident workgroups, 3: one
- *          workgroup per line group).
+ *   kind 4 batched fused line kernel: bit 0 as above, bits 2-3 = grid
+ *          (0: one workgroup per line group; 1, 2, 3: a persistent grid of
+ *          1x, 2x, 4x the resident workgroups).
  * The process-wide table starts with every variant 0.  A plan copies the
  * table's choices for its sizes when it is created (sar_plan, sar_batch_plan);
  * the first plan of the process loads $SAR_AUTOTUNE_CACHE if that is set.

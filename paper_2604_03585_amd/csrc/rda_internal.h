@@ -64,8 +64,8 @@ hipError_t launch_line(LineOp op, int n, const void* in, void* out, int lines, c
 int twiddle_table_size(int n);
 
 // Batched launches (kind: 0 fused, 1 forward, 2 inverse; tasks in device memory).
-//  variant bits 0 (twiddles) and 2-3 (persistent grid: 2x, 1x, 4x resident
-//  workgroups, or one workgroup per line group)
+//  variant bits 0 (twiddles) and 2-3 (grid: one workgroup per line group, or
+//  a persistent grid of 1x, 2x, 4x the resident workgroups)
 hipError_t launch_line_batch(int kind, int n, const void* tasks, int ntasks, int total_groups,
                              float scale, int prec, int variant, hipStream_t s);
 

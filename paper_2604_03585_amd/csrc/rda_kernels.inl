@@ -113,6 +113,14 @@ template <int N> struct LineLaunch {
     static constexpr int T = LineGeom<N>::T;
     static constexpr int LPW = T >= 256 ? 1 : 256 / T;     // lines per workgroup
     static constexpr int BLOCK = LPW * T;
+    // Register policy of the fused FFT*H*IFFT kernels (measured on gfx950):
+    // the inverse transform reuses the forward pass's twiddle products when
+    // the compiler can prove the addresses equal, which saves VALU work but
+    // keeps them live across the multiply.  For N = 4096 that reuse pays once
+    // the kernel is held to 128 VGPRs (4 waves per SIMD, as many workgroups
+    // as LDS allows); for N >= 8192 it spills, so the inverse recomputes them.
+    static constexpr int WPE = N == 4096 ? 4 : 1;          // minimum waves per SIMD
+    static constexpr bool RECOMPUTE_INV_TW = N >= 8192;
     static constexpr int LDS_BYTES = LPW * LineGeom<N>::LDS * (int)sizeof(float2);
 };
 
@@ -192,7 +200,9 @@ __device__ __forceinline__ void line_group(const float2* in, float2* out, int li
         });
 #pragma unroll
         for (int m = 0; m < E; ++m) x[m] = c_mul(x[m], h[m]);
-        fft_any<N, true, PREC, TWP>(x, lds, tw, sub, t);
+        int ti = t;
+        if constexpr (L::RECOMPUTE_INV_TW) asm volatile("" : "+v"(ti));   // hide ti == t
+        fft_any<N, true, PREC, TWP>(x, lds, tw, sub, ti);
     } else {
         fft_any<N, KIND == LK_INV, PREC, TWP>(x, lds, tw, sub, t);
         if (scale != 1.0f) {
@@ -204,7 +214,8 @@ __device__ __forceinline__ void line_group(const float2* in, float2* out, int li
 }
 
 template <int N, int KIND, int PREC, bool TWP>
-__global__ __launch_bounds__(LineLaunch<N>::BLOCK) void
+__global__ __launch_bounds__(LineLaunch<N>::BLOCK)
+__attribute__((amdgpu_waves_per_eu(LineLaunch<N>::WPE))) void
 k_line(const float2* in, float2* out, int lines, const float2* __restrict__ H,
        const float2* __restrict__ tw, float scale)
 {
@@ -216,22 +227,39 @@ k_line(const float2* in, float2* out, int lines, const float2* __restrict__ H,
 // grid covers min(total groups, resident capacity) workgroups, each walking
 // groups gg = blockIdx.x, + gridDim.x, ...; the task of a group is found by
 // binary search over the tasks' first-group indices (sorted).
-template <int N, int KIND, int PREC, bool TWP>
-__global__ __launch_bounds__(LineLaunch<N>::BLOCK) void
+// The task owning line group gg (tasks sorted by group_begin; uniform).
+__device__ __forceinline__ const LineTask& find_task(const LineTask* __restrict__ tasks, int ntasks,
+                                                      int gg)
+{
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tasks[mid].group_begin <= gg) lo = mid;
+        else hi = mid - 1;
+    }
+    return tasks[lo];
+}
+
+// PERSIST: a grid smaller than the work loops over line groups; otherwise
+// one workgroup per line group (no loop, so nothing is hoisted across
+// groups and the register footprint equals k_line's).
+template <int N, int KIND, int PREC, bool TWP, bool PERSIST>
+__global__ __launch_bounds__(LineLaunch<N>::BLOCK)
+__attribute__((amdgpu_waves_per_eu(LineLaunch<N>::WPE))) void
 k_line_batch(const LineTask* __restrict__ tasks, int ntasks, int total_groups, float scale)
 {
     extern __shared__ float2 smem[];
-    for (int gg = blockIdx.x; gg < total_groups; gg += gridDim.x) {
-        int lo = 0, hi = ntasks - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tasks[mid].group_begin <= gg) lo = mid;
-            else hi = mid - 1;
-        }
-        const LineTask tk = tasks[lo];
+    if constexpr (!PERSIST) {
+        const LineTask& tk = find_task(tasks, ntasks, blockIdx.x);
         line_group<N, KIND, PREC, TWP>(tk.in, tk.out, tk.lines, tk.H, tk.tw, scale,
-                                       gg - tk.group_begin, smem);
-        __syncthreads();                          // LDS reuse by the next group
+                                       blockIdx.x - tk.group_begin, smem);
+    } else {
+        for (int gg = blockIdx.x; gg < total_groups; gg += gridDim.x) {
+            const LineTask tk = find_task(tasks, ntasks, gg);
+            line_group<N, KIND, PREC, TWP>(tk.in, tk.out, tk.lines, tk.H, tk.tw, scale,
+                                           gg - tk.group_begin, smem);
+            __syncthreads();                      // LDS reuse by the next group
+        }
     }
 }
 
@@ -832,12 +860,18 @@ static hipError_t set_lds_limit()
                          (const void*)k_line<N, LK_INV, PREC, false>,
                          (const void*)k_rcmc_az<N, 0, PREC>, (const void*)k_rcmc_az<N, 8, PREC>,
                          (const void*)k_rcmc_az2<N, PREC>,
-                         (const void*)k_line_batch<N, LK_FUSED, PREC, true>,
-                         (const void*)k_line_batch<N, LK_FWD, PREC, true>,
-                         (const void*)k_line_batch<N, LK_INV, PREC, true>,
-                         (const void*)k_line_batch<N, LK_FUSED, PREC, false>,
-                         (const void*)k_line_batch<N, LK_FWD, PREC, false>,
-                         (const void*)k_line_batch<N, LK_INV, PREC, false>};
+                         (const void*)k_line_batch<N, LK_FUSED, PREC, true, true>,
+                         (const void*)k_line_batch<N, LK_FWD, PREC, true, true>,
+                         (const void*)k_line_batch<N, LK_INV, PREC, true, true>,
+                         (const void*)k_line_batch<N, LK_FUSED, PREC, false, true>,
+                         (const void*)k_line_batch<N, LK_FWD, PREC, false, true>,
+                         (const void*)k_line_batch<N, LK_INV, PREC, false, true>,
+                         (const void*)k_line_batch<N, LK_FUSED, PREC, true, false>,
+                         (const void*)k_line_batch<N, LK_FWD, PREC, true, false>,
+                         (const void*)k_line_batch<N, LK_INV, PREC, true, false>,
+                         (const void*)k_line_batch<N, LK_FUSED, PREC, false, false>,
+                         (const void*)k_line_batch<N, LK_FWD, PREC, false, false>,
+                         (const void*)k_line_batch<N, LK_INV, PREC, false, false>};
     for (const void* f : fns) {
         const hipError_t e =
             hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, L::LDS_BYTES);
@@ -899,6 +933,27 @@ static hipError_t launch_line_n(LineOp op, const float2* in, float2* out, int li
     return hipErrorInvalidValue;
 }
 
+template <int N, int PREC, bool TWP, bool PERSIST>
+static void launch_line_batch_k(int kind, int grid, const LineTask* tasks, int ntasks,
+                                int total_groups, float scale, hipStream_t s)
+{
+    using L = LineLaunch<N>;
+    switch (kind) {
+    case LK_FUSED:
+        hipLaunchKernelGGL((k_line_batch<N, LK_FUSED, PREC, TWP, PERSIST>), dim3(grid),
+                           dim3(L::BLOCK), L::LDS_BYTES, s, tasks, ntasks, total_groups, scale);
+        break;
+    case LK_FWD:
+        hipLaunchKernelGGL((k_line_batch<N, LK_FWD, PREC, TWP, PERSIST>), dim3(grid),
+                           dim3(L::BLOCK), L::LDS_BYTES, s, tasks, ntasks, total_groups, scale);
+        break;
+    default:
+        hipLaunchKernelGGL((k_line_batch<N, LK_INV, PREC, TWP, PERSIST>), dim3(grid),
+                           dim3(L::BLOCK), L::LDS_BYTES, s, tasks, ntasks, total_groups, scale);
+        break;
+    }
+}
+
 template <int N, int PREC, bool TWP>
 static hipError_t launch_line_batch_t(int kind, const LineTask* tasks, int ntasks, int total_groups,
                                       float scale, int grid_sel, hipStream_t s)
@@ -907,28 +962,18 @@ static hipError_t launch_line_batch_t(int kind, const LineTask* tasks, int ntask
     static const hipError_t attr = set_lds_limit<N, PREC>();
     if (attr != hipSuccess) return attr;
     if (total_groups == 0) return hipSuccess;
-    // Persistent grid: a multiple of the resident capacity (LDS-limited
-    // workgroups per CU x 256 CUs); grid_sel 0: 2x, 1: 1x, 2: 4x, 3: one
-    // workgroup per line group (not persistent).
+    // grid_sel 0: one workgroup per line group; 1, 2, 3: a persistent grid of
+    // 1x, 2x, 4x the resident workgroups (LDS-limited per CU x 256 CUs)
+    if ((grid_sel & 3) == 0) {
+        launch_line_batch_k<N, PREC, TWP, false>(kind, total_groups, tasks, ntasks, total_groups,
+                                                 scale, s);
+        return hipGetLastError();
+    }
     const int per_cu = (160 * 1024) / L::LDS_BYTES;
     const int resident = (per_cu < 1 ? 1 : per_cu) * 256;
-    const int mult[4] = {2, 1, 4, 0};
-    const int cap = mult[grid_sel & 3] ? resident * mult[grid_sel & 3] : total_groups;
+    const int cap = resident << ((grid_sel & 3) - 1);
     const int grid = total_groups < cap ? total_groups : cap;
-    switch (kind) {
-    case LK_FUSED:
-        hipLaunchKernelGGL((k_line_batch<N, LK_FUSED, PREC, TWP>), dim3(grid), dim3(L::BLOCK),
-                           L::LDS_BYTES, s, tasks, ntasks, total_groups, scale);
-        break;
-    case LK_FWD:
-        hipLaunchKernelGGL((k_line_batch<N, LK_FWD, PREC, TWP>), dim3(grid), dim3(L::BLOCK),
-                           L::LDS_BYTES, s, tasks, ntasks, total_groups, scale);
-        break;
-    default:
-        hipLaunchKernelGGL((k_line_batch<N, LK_INV, PREC, TWP>), dim3(grid), dim3(L::BLOCK),
-                           L::LDS_BYTES, s, tasks, ntasks, total_groups, scale);
-        break;
-    }
+    launch_line_batch_k<N, PREC, TWP, true>(kind, grid, tasks, ntasks, total_groups, scale, s);
     return hipGetLastError();
 }
 

@@ -6,8 +6,8 @@
 //       (FP32 butterflies only; the MFMA variants share one scheme);
 //   RCMC + azimuth kernel: the same twiddle choice for its IFFT, and two
 //       output rows per line slot (shared interpolation gathers) or one;
-//   batched fused line kernel: twiddles and the persistent grid size (1x, 2x
-//       or 4x the resident workgroups, or one workgroup per line group).
+//   batched fused line kernel: twiddles and the grid (one workgroup per line
+//       group, or a persistent grid of 1x, 2x or 4x the resident workgroups).
 // Every candidate computes the same result (they differ in instruction mix and
 // scheduling only); the tests check each one against the oracle.
 //
