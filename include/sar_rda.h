@@ -169,10 +169,10 @@ sar_status sar_rcmc_azimuth(sar_plan_t plan, const void* A_dev, void* out_dev,
  * generators).  which: 0 H_r (Nr complex64, includes 1/Nr), 1 H_a (Na
  * complex64, includes 1/Na; LFM only), 2 RCMC stretch 1/D-1 (Na doubles;
  * hyperbolic), 3 phase rate 2D/lambda (Na doubles; hyperbolic), 4 RCMC
- * weight coefficients (2048 floats; hyperbolic): 64 intervals of x in
+ * weight coefficients (3072 floats; hyperbolic): 128 intervals of x in
  * [0, 1), on interval b the weight of tap t (t = 0..7 for taps -3..4) is
- * sum_j c[(t*4 + j)*64 + b] u^j with u = 64 x - b (a cubic fitted at four
- * Chebyshev nodes to the exact FP64 Kaiser-sinc weights).
+ * sum_j c[b*24 + t*3 + j] u^j with u = 128 x - b (a quadratic fitted at
+ * three Chebyshev nodes to the exact FP64 Kaiser-sinc weights).
  * host_bytes must be at least the table size. Synchronous. */
 sar_status sar_plan_get_table(sar_plan_t plan, int32_t which, void* host_dst,
                               size_t host_bytes);

@@ -51,7 +51,8 @@ SAR_FP32, SAR_SPLIT_FP16, SAR_SPLIT_BF16 = 0, 1, 2
 SAR_FUSED, SAR_UNFUSED = 0, 1
 
 TABLE_HR, TABLE_HA, TABLE_STRETCH, TABLE_RATE, TABLE_RCMC = 0, 1, 2, 3, 4
-RCMC_INTERVALS = 64
+RCMC_INTERVALS = 128
+RCMC_PER_INTERVAL = 24          # 8 taps x 3 quadratic coefficients
 
 
 class sar_params(ctypes.Structure):
@@ -246,7 +247,7 @@ def sar_plan_get_table(plan, which: int):
     elif which == TABLE_HA:
         out = np.empty(na, np.complex64)
     elif which == TABLE_RCMC:
-        out = np.empty(8 * 4 * RCMC_INTERVALS, np.float32)
+        out = np.empty(RCMC_PER_INTERVAL * RCMC_INTERVALS, np.float32)
     else:
         out = np.empty(na, np.float64)
     _check(_sar_plan_get_table(plan, which, out.ctypes.data, out.nbytes), "sar_plan_get_table")

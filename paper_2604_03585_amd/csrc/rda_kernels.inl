@@ -91,20 +91,6 @@ __global__ void k_gen_chirp_filter(float2* __restrict__ H, int n, int len, doubl
     H[k] = make_float2((float)(re * scale), (float)(-im * scale));
 }
 
-// Hyperbolic per-Doppler-bin tables: f_k in fftfreq order (PRF = 1),
-// x = lam f / (2 v), D = sqrt(1 - x^2); stretch = x^2 / (D (1 + D)) (= 1/D - 1
-// without cancellation); rate = 2 D / lam (azimuth phase in turns per cell).
-__global__ void k_gen_hyper_tables(double* __restrict__ stretch, double* __restrict__ rate,
-                                   int na, double lam, double v)
-{
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= na) return;
-    const double f = (k < na / 2) ? (double)k / na : (double)(k - na) / na;
-    const double x = lam * f / (2.0 * v);
-    const double D = sqrt(1.0 - x * x);
-    stretch[k] = x * x / (D * (1.0 + D));
-    rate[k] = 2.0 * D / lam;
-}
 
 #endif  // SAR_PART == 0
 
@@ -219,7 +205,7 @@ __attribute__((amdgpu_waves_per_eu(LineLaunch<N>::WPE))) void
 k_line(const float2* in, float2* out, int lines, const float2* __restrict__ H,
        const float2* __restrict__ tw, float scale)
 {
-    extern __shared__ float2 smem[];
+    extern __shared__ __align__(16) float2 smem[];
     line_group<N, KIND, PREC, TWP>(in, out, lines, H, tw, scale, blockIdx.x, smem);
 }
 
@@ -248,7 +234,7 @@ __global__ __launch_bounds__(LineLaunch<N>::BLOCK)
 __attribute__((amdgpu_waves_per_eu(LineLaunch<N>::WPE))) void
 k_line_batch(const LineTask* __restrict__ tasks, int ntasks, int total_groups, float scale)
 {
-    extern __shared__ float2 smem[];
+    extern __shared__ __align__(16) float2 smem[];
     if constexpr (!PERSIST) {
         const LineTask& tk = find_task(tasks, ntasks, blockIdx.x);
         line_group<N, KIND, PREC, TWP>(tk.in, tk.out, tk.lines, tk.H, tk.tw, scale,
@@ -346,15 +332,17 @@ __global__ __launch_bounds__(256) void k_corner_turn_batch(const TurnTask* __res
 // The 8-tap Kaiser-windowed sinc (taps t = -3..4 about floor(p), x = p -
 // floor(p), weights normalised to unit sum) depends on x alone.  Its eight
 // weight functions w_t(x) are smooth on [0, 1), so the plan stores them as
-// piecewise cubics: RCMC_INTERVALS intervals, on each a degree-3 Chebyshev
-// interpolant of the exact FP64 weights, in monomial form in the local
-// variable u = x * RCMC_INTERVALS - b in [0, 1].  Layout (coefficient-major,
-// so that lanes with different intervals hit different LDS banks):
-//     tab[(t * 4 + j) * RCMC_INTERVALS + b] = coefficient of u^j, tap t.
-// The interpolation error is below 1e-7 of the weights (tested against the
-// oracle's weights); the kernels copy the 8 KiB table into LDS.
-constexpr int RCMC_INTERVALS = 64;
-constexpr int RCMC_TAB = 8 * 4 * RCMC_INTERVALS;
+// piecewise quadratics: RCMC_INTERVALS intervals, on each a degree-2
+// Chebyshev interpolant of the exact FP64 weights, in monomial form in the
+// local variable u = x * RCMC_INTERVALS - b in [0, 1].  Layout (interval-
+// major, 24 floats = 96 bytes per interval, read as six 16-byte vectors):
+//     tab[b * 24 + t * 3 + j] = coefficient of u^j, tap t.
+// The interpolation error is 2.2e-8 in FP64 (below the FP32 rounding of the
+// coefficients; tested against the oracle's weights); the kernels copy the
+// 12 KiB table into LDS.
+constexpr int RCMC_INTERVALS = 128;
+constexpr int RCMC_PER_INTERVAL = 24;
+constexpr int RCMC_TAB = RCMC_INTERVALS * RCMC_PER_INTERVAL;
 
 #if SAR_PART == 0
 __device__ double i0_fp64(double y)
@@ -384,40 +372,42 @@ __device__ void kaiser_weights_fp64(double x, double beta, double* w)
     for (int i = 0; i < 8; ++i) w[i] /= sum;
 }
 
-// One thread per interval b: Chebyshev nodes, exact weights, 4x4 solve.
+// One thread per interval b: three Chebyshev nodes, exact weights, 3x3
+// solve per tap for the monomial coefficients in u.
 __global__ void k_gen_rcmc_table(float* __restrict__ tab, double beta)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= RCMC_INTERVALS) return;
-    double u[4], w[4][8];
-    for (int j = 0; j < 4; ++j) {
-        u[j] = 0.5 * (1.0 + cospi((2.0 * j + 1.0) / 8.0));
+    double u[3], w[3][8];
+    for (int j = 0; j < 3; ++j) {
+        u[j] = 0.5 * (1.0 + cospi((2.0 * j + 1.0) / 6.0));
         kaiser_weights_fp64(((double)b + u[j]) / RCMC_INTERVALS, beta, w[j]);
     }
     for (int t = 0; t < 8; ++t) {
-        double M[4][5];
-        for (int j = 0; j < 4; ++j) {
-            double pw = 1.0;
-            for (int p = 0; p < 4; ++p) { M[j][p] = pw; pw *= u[j]; }
-            M[j][4] = w[j][t];
+        double M[3][4];
+        for (int j = 0; j < 3; ++j) {
+            M[j][0] = 1.0;
+            M[j][1] = u[j];
+            M[j][2] = u[j] * u[j];
+            M[j][3] = w[j][t];
         }
-        for (int c = 0; c < 4; ++c) {             // Gaussian elimination, partial pivot
+        for (int c = 0; c < 3; ++c) {             // Gaussian elimination, partial pivot
             int piv = c;
-            for (int r = c + 1; r < 4; ++r)
+            for (int r = c + 1; r < 3; ++r)
                 if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
-            for (int q = 0; q < 5; ++q) { double tmp = M[c][q]; M[c][q] = M[piv][q]; M[piv][q] = tmp; }
-            for (int r = c + 1; r < 4; ++r) {
+            for (int q = 0; q < 4; ++q) { double tmp = M[c][q]; M[c][q] = M[piv][q]; M[piv][q] = tmp; }
+            for (int r = c + 1; r < 3; ++r) {
                 const double f = M[r][c] / M[c][c];
-                for (int q = c; q < 5; ++q) M[r][q] -= f * M[c][q];
+                for (int q = c; q < 4; ++q) M[r][q] -= f * M[c][q];
             }
         }
-        double cf[4];
-        for (int c = 3; c >= 0; --c) {
-            double acc = M[c][4];
-            for (int q = c + 1; q < 4; ++q) acc -= M[c][q] * cf[q];
+        double cf[3];
+        for (int c = 2; c >= 0; --c) {
+            double acc = M[c][3];
+            for (int q = c + 1; q < 3; ++q) acc -= M[c][q] * cf[q];
             cf[c] = acc / M[c][c];
         }
-        for (int j = 0; j < 4; ++j) tab[(t * 4 + j) * RCMC_INTERVALS + b] = (float)cf[j];
+        for (int j = 0; j < 3; ++j) tab[b * RCMC_PER_INTERVAL + t * 3 + j] = (float)cf[j];
     }
 }
 
@@ -434,19 +424,44 @@ struct RcmcArgs {
     int nr;
 };
 
-// The per-bin geometry computed from the bin index, exactly as the plan's
-// tables are built: f_k in fftfreq order, x = lambda f / (2 v),
-// D = sqrt(1 - x^2), stretch = x^2 / (D (1 + D)), rate = 2 D / lambda.
+// The per-bin geometry from the bin index: f_k in fftfreq order,
+// x = lambda f / (2 v), D = sqrt(1 - x^2), stretch = 1/D - 1, rate = 2 D / lambda.
+// r = 1/D comes from the hardware reciprocal square root refined by two
+// Newton steps in FP64 (quadratic convergence: full double precision), so
+// stretch = r - 1 has an absolute error near 1e-16; the RCMC shift
+// R0 * stretch needs it to 1e-12.  The plan's tables use the same function.
+__device__ __forceinline__ void bin_geometry_x(double x, double two_over_lam, double& stretch,
+                                               double& rate)
+{
+    const double a = fma(-x, x, 1.0);               // D^2
+    double r = __builtin_amdgcn_rsq(a);
+    const double ha = 0.5 * a;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) r = r * fma(-ha * r, r, 1.5);
+    stretch = r - 1.0;
+    rate = (a * r) * two_over_lam;                  // D = a / sqrt(a)
+}
+
 __device__ __forceinline__ void bin_geometry(const RcmcArgs& ra, int k, int na, double& stretch,
                                              double& rate)
 {
     const int kk = k < na / 2 ? k : k - na;
-    const double x = (double)kk * ra.x_per_bin;
-    const double x2 = x * x;
-    const double D = sqrt(1.0 - x2);
-    stretch = x2 / (D * (1.0 + D));
-    rate = D * ra.two_over_lam;
+    bin_geometry_x((double)kk * ra.x_per_bin, ra.two_over_lam, stretch, rate);
 }
+
+#if SAR_PART == 0
+// Hyperbolic per-Doppler-bin tables (the unfused and one-row kernels read
+// them; the two-row kernel computes the same values in place):
+// stretch = 1/D - 1, rate = 2 D / lambda (azimuth phase in turns per cell).
+__global__ void k_gen_hyper_tables(double* __restrict__ stretch, double* __restrict__ rate,
+                                   int na, double x_per_bin, double two_over_lam)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= na) return;
+    const int kk = k < na / 2 ? k : k - na;
+    bin_geometry_x((double)kk * x_per_bin, two_over_lam, stretch[k], rate[k]);
+}
+#endif
 
 __device__ __forceinline__ void load_rcmc_table(float* __restrict__ lds_tab,
                                                 const float* __restrict__ tab, int tid, int nthreads)
@@ -461,17 +476,26 @@ __device__ __forceinline__ float2 rcmc_combine(float x, const float* __restrict_
     const float xf = x * (float)RCMC_INTERVALS;
     const int b = min((int)xf, RCMC_INTERVALS - 1);
     const float u = xf - (float)b;
-    const float* p = tab + b;
+    const float4* p = (const float4*)(tab + b * RCMC_PER_INTERVAL);
     float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const float c0 = p[(t * 4 + 0) * RCMC_INTERVALS];
-        const float c1 = p[(t * 4 + 1) * RCMC_INTERVALS];
-        const float c2 = p[(t * 4 + 2) * RCMC_INTERVALS];
-        const float c3 = p[(t * 4 + 3) * RCMC_INTERVALS];
-        const float w = fmaf(fmaf(fmaf(c3, u, c2), u, c1), u, c0);
-        acc.x = fmaf(w, a[t].x, acc.x);
-        acc.y = fmaf(w, a[t].y, acc.y);
+    for (int h = 0; h < 2; ++h) {                 // taps 4h .. 4h+3: three vectors
+        float c[12];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const float4 v = p[3 * h + i];
+            c[4 * i] = v.x;
+            c[4 * i + 1] = v.y;
+            c[4 * i + 2] = v.z;
+            c[4 * i + 3] = v.w;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t = 4 * h + q;
+            const float w = fmaf(fmaf(c[3 * q + 2], u, c[3 * q + 1]), u, c[3 * q]);
+            acc.x = fmaf(w, a[t].x, acc.x);
+            acc.y = fmaf(w, a[t].y, acc.y);
+        }
     }
     return acc;
 }
@@ -533,12 +557,16 @@ __device__ __forceinline__ float2 rcmc_value(const float2* __restrict__ A, int n
 // exp(+j 2 pi frac(R0 * rate)) * scale: the phase in turns is reduced in
 // FP64, then the hardware sine/cosine (argument in turns, max abs error
 // 1.3e-7 on [-1/2, 1/2], measured on gfx950) evaluate it.
-__device__ __forceinline__ float2 az_phase_of(double R0, double rate, float scale)
+__device__ __forceinline__ float2 turns_to_phasor(double ph, float scale)
 {
-    const double ph = R0 * rate;
     float f = (float)(ph - floor(ph));
     if (f > 0.5f) f -= 1.0f;
     return make_float2(__builtin_amdgcn_cosf(f) * scale, __builtin_amdgcn_sinf(f) * scale);
+}
+
+__device__ __forceinline__ float2 az_phase_of(double R0, double rate, float scale)
+{
+    return turns_to_phasor(R0 * rate, scale);
 }
 
 __device__ __forceinline__ float2 az_phase(const RcmcArgs& ra, int n, int k, float scale)
@@ -614,7 +642,7 @@ k_rcmc_az(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
 {
     using L = LineLaunch<N>;
     constexpr int E = line_e(N);
-    extern __shared__ float2 smem[];
+    extern __shared__ __align__(16) float2 smem[];
     // The weight table and the line buffers share LDS: the table is only read
     // while the RCMC samples are formed, before the first FFT exchange.
     float* tab = (float*)smem;
@@ -694,18 +722,25 @@ struct ColPair {
     float2 pa, pb;       // azimuth phases (with 1/Na) for rows n, n+1
 };
 
+// Row n+1 continues row n: its shift is s + stretch and its phase (turns)
+// ph + rate, both in FP64 (the same values as R0 * stretch and R0 * rate
+// with R0 = r_near + n + 1, up to one rounding).
 __device__ __forceinline__ ColPair col_pair(const RcmcArgs& ra, int n, int k, int na, float scale)
 {
     double stretch, rate;
     bin_geometry(ra, k, na, stretch, rate);
     const double R0 = ra.r_near + (double)n;
     ColPair c;
-    int ib;
-    rcmc_shift(R0, n, stretch, c.xa, c.i0);
-    rcmc_shift(R0 + 1.0, n + 1, stretch, c.xb, ib);
-    c.d = (ib - c.i0) == 2;
-    c.pa = az_phase_of(R0, rate, scale);
-    c.pb = az_phase_of(R0 + 1.0, rate, scale);
+    const double sa = R0 * stretch, sb = sa + stretch;
+    const double fa = floor(sa), fb = floor(sb);
+    c.xa = (float)(sa - fa);
+    c.xb = (float)(sb - fb);
+    // shifts beyond +-2^30 cells read nothing but stay defined integers
+    c.i0 = n + (int)fmax(-1073741824.0, fmin(fa, 1073741824.0));
+    c.d = (fb - fa) != 0.0;                       // i0(n+1) - i0(n) == 2
+    const double pa = R0 * rate;
+    c.pa = turns_to_phasor(pa, scale);
+    c.pb = turns_to_phasor(pa + rate, scale);
     return c;
 }
 
@@ -760,7 +795,7 @@ k_rcmc_az2(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
 {
     using L = LineLaunch<N>;
     constexpr int E = line_e(N);
-    extern __shared__ float2 smem[];
+    extern __shared__ __align__(16) float2 smem[];
     float* tab = (float*)smem;                    // shares LDS with the line buffers
     const int pairs = ra.nr / 2;
     const int groups = (pairs + L::LPW - 1) / L::LPW;
@@ -797,7 +832,7 @@ template <int TAPS>
 __global__ __launch_bounds__(256) void k_rcmc_interp(const float2* __restrict__ A,
                                                      float2* __restrict__ out, int na, RcmcArgs ra)
 {
-    __shared__ float tab[RCMC_TAB];
+    __shared__ __align__(16) float tab[RCMC_TAB];
     if constexpr (TAPS != 0) {
         load_rcmc_table(tab, ra.table, threadIdx.x, 256);
         __syncthreads();
@@ -1206,8 +1241,9 @@ int rcmc_table_floats() { return RCMC_TAB; }
 hipError_t launch_gen_hyper_tables(double* stretch, double* rate, int na, double lam, double v,
                                    hipStream_t s)
 {
+    // the same expressions as the kernels' RcmcArgs (x_per_bin, two_over_lam)
     hipLaunchKernelGGL(k_gen_hyper_tables, dim3((na + 255) / 256), dim3(256), 0, s, stretch, rate,
-                       na, lam, v);
+                       na, lam / (2.0 * v * (double)na), 2.0 / lam);
     return hipGetLastError();
 }
 
