@@ -466,7 +466,9 @@ __global__ void k_gen_hyper_tables(double* __restrict__ stretch, double* __restr
 __device__ __forceinline__ void load_rcmc_table(float* __restrict__ lds_tab,
                                                 const float* __restrict__ tab, int tid, int nthreads)
 {
-    for (int i = tid; i < RCMC_TAB; i += nthreads) lds_tab[i] = tab[i];
+    static_assert(RCMC_TAB % 4 == 0, "16-byte copies");
+    for (int i = tid; i < RCMC_TAB / 4; i += nthreads)
+        ((float4*)lds_tab)[i] = ((const float4*)tab)[i];
 }
 
 // sum_t w_t(x) a_t with the weights from the LDS table.
