@@ -77,11 +77,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel: str):
+def recorded_traffic(kernel: str, profiles_dir: str | None = None):
     """HBM bytes per launch from the committed counter summary of ``kernel``
     (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's counts), if it was
     taken on the current kernel sources; else None."""
-    d = os.path.join(ROOT, "profiles")
+    d = profiles_dir or os.path.join(ROOT, "profiles")
     want = kernel_source_hash()
     if not os.path.isdir(d):
         return None
