@@ -104,11 +104,16 @@ template <int N> struct LineLaunch {
     // the compiler can prove the addresses equal, which saves VALU work but
     // keeps them live across the multiply.  For N = 4096 that reuse pays once
     // the kernel is held to 128 VGPRs (4 waves per SIMD, as many workgroups
-    // as LDS allows); for N >= 8192 it spills, so the inverse recomputes them.
-    static constexpr int WPE = N == 4096 ? 4 : 1;          // minimum waves per SIMD
+    // as LDS allows; see line_wpe); for N >= 8192 it spills, so the inverse
+    // recomputes them.
     static constexpr bool RECOMPUTE_INV_TW = N >= 8192;
     static constexpr int LDS_BYTES = LPW * LineGeom<N>::LDS * (int)sizeof(float2);
 };
+
+// Minimum waves per SIMD requested for the line kernels: 4 for the FP32
+// 4096-point kernels (register reuse above), no request otherwise (the
+// split-precision kernels need more than 128 VGPRs).
+template <int N, int PREC> constexpr int line_wpe() { return (N == 4096 && PREC == 0) ? 4 : 1; }
 
 // Line transform in the requested butterfly precision: FP32 VALU passes, or
 // split FP16 / BF16 radix-16 passes on MFMA (twiddles and filters in FP32).
@@ -201,7 +206,7 @@ __device__ __forceinline__ void line_group(const float2* in, float2* out, int li
 
 template <int N, int KIND, int PREC, bool TWP>
 __global__ __launch_bounds__(LineLaunch<N>::BLOCK)
-__attribute__((amdgpu_waves_per_eu(LineLaunch<N>::WPE))) void
+__attribute__((amdgpu_waves_per_eu(line_wpe<N, PREC>()))) void
 k_line(const float2* in, float2* out, int lines, const float2* __restrict__ H,
        const float2* __restrict__ tw, float scale)
 {
@@ -231,7 +236,7 @@ __device__ __forceinline__ const LineTask& find_task(const LineTask* __restrict_
 // groups and the register footprint equals k_line's).
 template <int N, int KIND, int PREC, bool TWP, bool PERSIST>
 __global__ __launch_bounds__(LineLaunch<N>::BLOCK)
-__attribute__((amdgpu_waves_per_eu(LineLaunch<N>::WPE))) void
+__attribute__((amdgpu_waves_per_eu(line_wpe<N, PREC>()))) void
 k_line_batch(const LineTask* __restrict__ tasks, int ntasks, int total_groups, float scale)
 {
     extern __shared__ __align__(16) float2 smem[];
