@@ -102,11 +102,10 @@ sar_status build(sar_batch_s* B, const void* const* raw, void* const* img, void*
         Bt[i] = back ? w : img[i];
         if (!batched(B->params[i])) B->fallback.push_back(i);
     }
-    auto add_line_stage = [&](bool range_stage) {
-        // group batched scenes by (line length, precision)
+    auto add_line_stage = [&](bool range_stage, const std::vector<int>& scenes) {
+        // group the scenes by (line length, precision)
         std::map<std::pair<int, int>, std::vector<int>> groups;
-        for (int i = 0; i < n; ++i) {
-            if (!batched(B->params[i])) continue;
+        for (int i : scenes) {
             const int len = range_stage ? B->params[i].Nr : B->params[i].Na;
             groups[{len, B->params[i].precision}].push_back(i);
         }
@@ -141,10 +140,9 @@ sar_status build(sar_batch_s* B, const void* const* raw, void* const* img, void*
             host.resize(align256(host.size()));
         }
     };
-    auto add_turn_stage = [&](bool back_turn) {
+    auto add_turn_stage = [&](bool back_turn, const std::vector<int>& scenes) -> sar_status {
         Launch L{1, 0, 0, 0, 0, host.size(), 0, 0};
-        for (int i = 0; i < n; ++i) {
-            if (!batched(B->params[i])) continue;
+        for (int i : scenes) {
             const sar_params& p = B->params[i];
             if (back_turn && !p.transpose_back) continue;
             sar::TurnTask t{};
@@ -159,6 +157,9 @@ sar_status build(sar_batch_s* B, const void* const* raw, void* const* img, void*
                 t.rows = p.Nr;
                 t.cols = p.Na;
             }
+            if (t.rows % 64 != 0 || t.cols % 64 != 0 || (((uintptr_t)t.in | (uintptr_t)t.out) & 15u))
+                return sar::set_error(SAR_ERR_BAD_PARAM, "scene %d: batched turn needs whole 64 x 64 tiles "
+                                      "and 16-byte aligned buffers", i);
             t.tile_begin = L.total;
             L.total += sar::turn_tiles(t.rows, t.cols);
             const char* b = (const char*)&t;
@@ -167,11 +168,16 @@ sar_status build(sar_batch_s* B, const void* const* raw, void* const* img, void*
         }
         if (L.ntasks) launches.push_back(L);
         host.resize(align256(host.size()));
+        return SAR_OK;
     };
-    add_line_stage(true);
-    add_turn_stage(false);
-    add_line_stage(false);
-    add_turn_stage(true);
+    std::vector<int> scenes;
+    for (int i = 0; i < n; ++i)
+        if (batched(B->params[i])) scenes.push_back(i);
+    add_line_stage(true, scenes);
+    sar_status st = add_turn_stage(false, scenes);
+    if (st != SAR_OK) return st;
+    add_line_stage(false, scenes);
+    if ((st = add_turn_stage(true, scenes)) != SAR_OK) return st;
 
     if (host.size() > B->dev_tasks_cap) {
         if (B->dev_tasks) (void)hipFree(B->dev_tasks);
