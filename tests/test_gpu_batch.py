@@ -20,13 +20,16 @@ pytestmark = pytest.mark.gpu
 
 
 def small_batch():
-    """Uneven small scenes: LFM of several sizes, one with transpose_back,
+    """Uneven small scenes: LFM of several sizes (two of them in split FP16 /
+    split BF16, batched with their own launches), one with transpose_back,
     one hyperbolic and one unfused (both run outside the batched launches)."""
     cfgs = [c for c in batch_configs(seed=4, n=64, nr_choices=(256, 512, 1024),
                                      na_choices=(256, 512))][:6]
     hyp = config("c2", Nr=512, Na=2048, range_len=256, range_tbp=100.0, n_targets=1, seed=9)
-    return cfgs, [dict() for _ in cfgs] + [dict(), dict(schedule="unfused"),
-                                          dict(transpose_back=1)], hyp
+    opts = [dict() for _ in cfgs]
+    opts[1] = dict(precision="split_fp16")
+    opts[4] = dict(precision="split_bf16")
+    return cfgs, opts + [dict(), dict(schedule="unfused"), dict(transpose_back=1)], hyp
 
 
 def run_batch(cfgs, opts, scenes, stream, reps=1):

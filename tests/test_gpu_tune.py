@@ -60,6 +60,13 @@ def test_autotune_writes_cache_and_plans_use_it(tmp_path, name):
     cfg, sc, ref = scene(name)
     path = tmp_path / "tune.jsonl"
     sar.sar_autotune(sar.make_params(cfg), str(path))
+    # split precisions are tuned under their own keys (prec 1) in the same file
+    sar.sar_autotune(sar.make_params(cfg, precision="split_fp16"), str(path))
+    split = [json.loads(l) for l in path.read_text().splitlines() if json.loads(l)["prec"] == 1]
+    assert split and all(e["variant"] in (0, 2, 4, 8, 12) for e in split), split
+    path.write_text("".join(l + "\n" for l in path.read_text().splitlines()
+                            if json.loads(l)["prec"] == 0))
+    sar.sar_tune_load(str(path))
     lines = [json.loads(l) for l in path.read_text().splitlines()]
     kinds = {(e["kind"], e["n"]) for e in lines}
     if cfg["az_model"] == "lfm":
