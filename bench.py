@@ -16,6 +16,8 @@ Besides the headline it measures, each on the same GPU:
   unfused       the 3-dispatch comparator;
   split         the same scene with radix-16 butterflies on MFMA (split
                 FP16 / BF16 operands, FP32 accumulation);
+  fft_batched   batched 4096-point line FFTs alone (batch 256 and 4096), FP32
+                and split precisions, in GFLOPS;
   batch         64 scenes of uneven size (LFM, Nr 1024..16384, Na 512..8192)
                 in shared launches replayed from a hipGraph, autotuned, vs the
                 same scenes run one after another;
@@ -58,6 +60,7 @@ def parse():
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-fft", action="store_true")
     ap.add_argument("--no-cold", action="store_true",
                     help="skip the cold-MALL steps (profiling runs: keeps every "
                          "dispatch of a kernel under the pipeline's cache state)")
@@ -196,6 +199,29 @@ def headline(args, torch, sar, cfg, raw, dev):
     plan.close()
     uplan.close()
     return ms_event, ms_wall, ms_cold, kern, ms_unfused, split, images
+
+
+def fft_leg(torch, sar, dev):
+    """Batched line FFTs alone (the paper's Table I setting: N = 4096, batch
+    256; also batch 4096): GFLOPS at 5 N log2 N per transform, FP32 radix-16
+    Stockham vs the split FP16 / BF16 MFMA butterflies."""
+    from sarsim import lfm_scene
+    s = torch.cuda.current_stream()
+    out = {"n": 4096, "flops_per_fft": 5 * 4096 * 12}
+    for batch in (256, 4096):
+        cfg = lfm_scene(4096, batch, 1, 1, "fft")
+        a = torch.randn(batch * 4096, dtype=torch.complex64, device=dev)
+        b = torch.empty_like(a)
+        for prec in ("fp32", "split_fp16", "split_bf16"):
+            with sar.Plan(cfg, precision=prec) as p:
+                ms, _ = Timer(torch, s)(lambda: sar.sar_fft_lines(p.handle, 0, 0, a, b, batch, s),
+                                        200 if batch == 256 else 50, 5)
+            out[f"batch{batch}_{prec}"] = {
+                "us": round(ms * 1e3, 2),
+                "gflops": round(5 * 4096 * 12 * batch / (ms * 1e-3) / 1e9, 1),
+                "hbm_frac": round(16 * 4096 * batch / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
+    out["paper_context"] = "Apple M1 radix-8 Stockham 138 GFLOPS, MMA CT DIF 128 GFLOPS (Table I)"
+    return out
 
 
 def batch_leg(torch, sar, dev):
@@ -417,6 +443,9 @@ def main():
     if split:
         out["split"] = split
 
+    if not args.no_fft:
+        out["fft_batched"] = fft_leg(torch, sar, dev)
+        log(f"fft: {out['fft_batched']}")
     if not args.no_batch:
         out["batch"] = batch_leg(torch, sar, dev)
         log(f"batch: {out['batch']}")
