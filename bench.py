@@ -341,9 +341,16 @@ def serve_leg(args, torch, sar, dev):
 
 
 def accuracy(images, sc, ref, cfg):
+    """Per precision: relative L2 against the oracle image and the largest
+    PSLR / ISLR / SNR differences over the targets; plus the per-target
+    quality of the FP32 image (the analogue of the paper's Table IV)."""
     from oracle import quality as Q
     rep_ref = Q.point_target_report(ref, sc.targets, 64, 64)
-    acc = {}
+    acc = {"targets_fp32": [
+        {"cell": list(r["peak"]), **{k: round(float(r[k]), 3) for k in
+                                    ("snr_db", "pslr_range", "islr_range", "pslr_azimuth",
+                                     "islr_azimuth")}}
+        for r in Q.point_target_report(images["fp32"].T, sc.targets, 64, 64)]}
     for prec, im in images.items():
         img = im.T
         rep = Q.point_target_report(img, sc.targets, 64, 64)
