@@ -177,21 +177,45 @@ sar_status sar_rcmc_azimuth(sar_plan_t plan, const void* A_dev, void* out_dev,
 sar_status sar_plan_get_table(sar_plan_t plan, int32_t which, void* host_dst,
                               size_t host_bytes);
 
-/* ---- batched execution (scenes of uneven size) ---- */
+/* ---- batched execution (scenes of uneven size) ----
+ *
+ * Not in the paper: the batching pattern for many scenes.  Scenes with LFM
+ * azimuth and the fused schedule share launches: one line launch per (pass,
+ * line length, precision) and one corner-turn launch per turn, each a grid
+ * over all scenes' line groups or tiles (task lists in device memory).  Every
+ * other scene (hyperbolic, unfused) runs as sar_rda_execute in the same
+ * stream.  Each scene's image is bit-identical to its own sar_rda_execute.
+ */
 
-/* Plan `n` scenes (params ps[0..n-1]) for one batched execution. */
+/* Plan `n` scenes (params ps[0..n-1], n >= 1): validates every parameter set
+ * (errors as sar_plan, reported for the first invalid scene), builds one plan
+ * per distinct parameter set on `stream` (synchronised), and lays out the
+ * scenes' workspaces in one buffer.  *out receives the batch. */
 sar_status sar_batch_plan(const sar_params* ps, int32_t n, void* stream,
                           sar_batch_t* out);
 
-/* Device workspace bytes for sar_batch_execute (sum over scenes). */
+/* Device workspace bytes for sar_batch_execute: the scenes' workspaces,
+ * each 256-byte aligned.  0 for a NULL batch. */
 size_t sar_batch_workspace_bytes(sar_batch_t batch);
 
 /* Run every scene: raw_dev[i] [Na_i][Nr_i] -> img_dev[i] (layout as in
- * sar_rda_execute).  raw/img are host arrays of n device pointers; work_dev
- * holds sar_batch_workspace_bytes(batch).  Asynchronous on `stream`. */
+ * sar_rda_execute).  raw_dev / img_dev are host arrays of n device pointers
+ * (16-byte aligned); work_dev holds sar_batch_workspace_bytes(batch).  The
+ * images and the workspace must not overlap each other or any raw input
+ * (SAR_ERR_ALIAS); raw inputs are only read and may be shared by scenes.
+ * The first call with a set of buffer pointers (and stream) builds the task
+ * lists and uploads them synchronously (after synchronising the stream of
+ * the previous set, whose replays may still read them); on a non-null stream
+ * it then captures the whole batch into a hipGraph, and every later call with
+ * the same pointers replays that graph (asynchronous).  On the null stream
+ * the launches are issued directly.  Errors: SAR_ERR_NULL, SAR_ERR_BAD_PARAM
+ * (misaligned buffers, another device than at planning), SAR_ERR_ALIAS,
+ * SAR_ERR_NO_MEMORY (task buffer), SAR_ERR_HIP. */
 sar_status sar_batch_execute(sar_batch_t batch, const void* const* raw_dev,
                              void* const* img_dev, void* work_dev, void* stream);
 
+/* Free the batch, its plans, task buffer and graph (NULL is a no-op).  The
+ * caller must first synchronise any stream a replay of it was queued on. */
 void sar_batch_destroy(sar_batch_t batch);
 
 /* ---- autotuner (the batching/serving pattern: measured kernel choices) ----

@@ -274,10 +274,14 @@ sar_status sar_batch_execute(sar_batch_t B, const void* const* raw, void* const*
         if (overlap(raw[i], bytes, img[i], bytes) ||
             overlap(raw[i], bytes, work, B->work_bytes) || overlap(img[i], bytes, work, B->work_bytes))
             return sar::set_error(SAR_ERR_ALIAS, "scene %d: raw, img and work must be disjoint", i);
-        for (int j = 0; j < i; ++j) {
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
             const size_t bj = (size_t)B->params[j].Na * B->params[j].Nr * 8;
-            if (overlap(img[i], bytes, img[j], bj))
+            if (j < i && overlap(img[i], bytes, img[j], bj))
                 return sar::set_error(SAR_ERR_ALIAS, "scenes %d and %d share an image buffer", j, i);
+            if (!raw[j]) return sar::set_error(SAR_ERR_NULL, "scene %d: raw is NULL", j);
+            if (overlap(img[i], bytes, raw[j], bj))
+                return sar::set_error(SAR_ERR_ALIAS, "image %d overlaps raw input %d", i, j);
         }
     }
     hipStream_t s = (hipStream_t)stream;

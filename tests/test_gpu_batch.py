@@ -86,3 +86,32 @@ def test_batch_against_oracle():
         assert rel_l2(img.T, ref) <= 1e-5, c["name"]
         for t in s.targets:
             assert Q.peak_cell(img.T, t["m"], t["n"]) == (t["m"], t["n"])
+
+
+def test_batch_buffer_rules():
+    """Shared raw inputs are allowed; images overlapping each other or another
+    scene's raw input are rejected before anything is launched."""
+    torch = torch_cuda()
+    cfgs = batch_configs(seed=4, n=64, nr_choices=(256,), na_choices=(256,))[:2]
+    params = [sar.make_params(c) for c in cfgs]
+    b = sar.sar_batch_plan(params, None)
+    try:
+        px = 256 * 256
+        raw = dev(simulate(cfgs[0]).raw)
+        pool = torch.empty(4 * px, dtype=torch.complex64, device="cuda")
+        img0, img1 = pool[:px], pool[px:2 * px]
+        work = torch.empty(sar.sar_batch_workspace_bytes(b) // 8 + 1, dtype=torch.complex64,
+                           device="cuda")
+        # the same raw for both scenes: fine, and both images equal
+        sar.sar_batch_execute(b, [raw, raw], [img0, img1], work, 0)
+        torch.cuda.synchronize()
+        assert torch.equal(img0.view(torch.int64), img1.view(torch.int64))
+        with pytest.raises(sar.SarError) as e:
+            sar.sar_batch_execute(b, [raw, raw], [img0, pool[px // 2:px // 2 + px]], work, 0)
+        assert e.value.status == sar._lib.SAR_ERR_ALIAS
+        with pytest.raises(sar.SarError) as e:
+            sar.sar_batch_execute(b, [raw, img0], [img0, img1], work, 0)   # image 0 = raw 1
+        assert e.value.status == sar._lib.SAR_ERR_ALIAS
+    finally:
+        torch.cuda.synchronize()
+        sar.sar_batch_destroy(b)
