@@ -91,6 +91,7 @@ def test_c5_full_pool_served_equals_alone():
     rng = np.random.default_rng(55)
     which = rng.integers(0, len(cfgs), size=48)
     arrivals = np.cumsum(rng.exponential(1 / 2000.0, size=48))
+    arrivals[:8] = 0.0                      # a burst first: requests must overlap
     mismatched = []
 
     def check(res):

@@ -47,6 +47,7 @@ def test_served_equals_alone(slots):
     # 60 requests, Poisson at ~5 kHz: several on the device at once
     _, which = poisson_arrivals(seed=21, n=60, rate_hz=5000.0, pool_size=len(cfgs))
     arrivals = np.cumsum(np.random.default_rng(21).exponential(1 / 5000.0, size=60))
+    arrivals[:8] = 0.0                      # a burst first: requests must overlap
     reqs = [(cfgs[w], raws[w], precs[k % 2]) for k, w in enumerate(which)]
     budget = 2 * max(footprint_bytes(c) for c in cfgs)
     ex = GpuExecutor(slots, budget)

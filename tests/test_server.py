@@ -180,7 +180,7 @@ def test_admitted_requests_overlap():
     wall = time.perf_counter() - t0
     srv.close()
     assert srv.max_concurrent == 4
-    assert wall < 0.25                                    # 8 x 50 ms in two waves, not serial
+    assert wall < 0.3                                     # 8 x 50 ms in two waves, not serial
 
 
 def test_launch_and_result_errors_are_isolated():
