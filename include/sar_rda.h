@@ -226,7 +226,9 @@ void sar_batch_destroy(sar_batch_t batch);
  *          variant bit 0 = twiddles read from the table (else by products
  *          of two table loads per radix-16 pass; FP32 butterflies only);
  *   kind 3 RCMC + azimuth kernel: bit 0 as above for its IFFT, bit 1 = one
- *          output row per line slot (else two rows sharing their gathers);
+ *          output row per line slot (else two rows sharing their gathers),
+ *          bit 2 = the two rows on two line slots' threads instead of one's
+ *          (FP32 and Na = 4096 or 8192 only);
  *   kind 4 batched fused line kernel: bit 0 as above, bits 2-3 = grid
  *          (0: one workgroup per line group; 1, 2, 3: a persistent grid of
  *          1x, 2x, 4x the resident workgroups).

@@ -800,13 +800,15 @@ __device__ __forceinline__ void rcmc_pair_combine(float2& ya, float2& yb, const 
     yb = c_mul(rcmc_combine(c.xb, tab, tb), c.pb);
 }
 
-template <int N, bool EDGE>
-__device__ __forceinline__ void rcmc_rows2(float2 (&xa)[line_e(N)], float2 (&xb)[line_e(N)],
+// Columns t + m * S (m < C) of rows n, n+1.
+template <int N, bool EDGE, int C = line_e(N), int S = LineGeom<N>::T>
+__device__ __forceinline__ void rcmc_rows2(float2 (&xa)[C], float2 (&xb)[C],
                                            const float2* __restrict__ A, const RcmcArgs& ra,
                                            int n, int t, const float* __restrict__ tab)
 {
-    constexpr int T = LineGeom<N>::T;
-    constexpr int E = line_e(N);
+    constexpr int T = S;
+    constexpr int E = C;
+    static_assert(E % 2 == 0, "columns are processed in pairs");
     constexpr float scale = 1.0f / (float)N;
     // two named buffers, alternated by column parity (no register copies)
     ColPair c0 = col_pair(ra, n, t, N, scale), c1;
@@ -864,6 +866,52 @@ k_rcmc_az2(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
     if (live) store_line<N>(xa, out + (size_t)n * N, t);
     fft_any<N, true, PREC>(xb, lds, tw, sub, t);
     if (live) store_line<N>(xb, out + (size_t)(n + 1) * N, t);
+}
+
+// The same two rows per workgroup on 2T threads (FP32, T = N/16 <= 512):
+// the interpolation is spread over all 2T threads (E/2 columns each, half
+// the accumulator registers of k_rcmc_az2), the two rows then meet in LDS
+// and their IFFTs run side by side, one per half of the workgroup.  LDS:
+// two line buffers (the weight table shares the first).
+template <int N>
+__global__ __launch_bounds__(2 * LineGeom<N>::T) void
+k_rcmc_az2w(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
+            const float2* __restrict__ tw)
+{
+    using G = LineGeom<N>;
+    constexpr int T = G::T, E = line_e(N), C = E / 2, S = 2 * T;
+    static_assert(S <= 1024, "two line slots per workgroup");
+    extern __shared__ __align__(16) float2 smem[];
+    float* tab = (float*)smem;
+    const int pairs = ra.nr / 2;
+    const int pr = xcd_group(blockIdx.x, pairs);
+    const int n = 2 * pr;
+    const int u = threadIdx.x;
+    load_rcmc_table(tab, ra.table, u, S);
+    __syncthreads();
+    float2 ya[C], yb[C];
+    const double smax = (ra.r_near + (double)n + 1.0) * ra.stretch_max;
+    if (n >= 3 && (double)n + 1.0 + smax + 6.0 <= (double)(ra.nr - 1))
+        rcmc_rows2<N, false, C, S>(ya, yb, A, ra, n, u, tab);
+    else
+        rcmc_rows2<N, true, C, S>(ya, yb, A, ra, n, u, tab);
+    __syncthreads();                              // table reads done before LDS reuse
+    float2* row_a = smem;
+    float2* row_b = smem + G::LDS;
+#pragma unroll
+    for (int m = 0; m < C; ++m) {
+        row_a[lds_pad(u + m * S)] = ya[m];
+        row_b[lds_pad(u + m * S)] = yb[m];
+    }
+    __syncthreads();
+    const int sub = u / T, t = u % T;
+    float2* lds = smem + sub * G::LDS;
+    float2 x[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) x[m] = lds[lds_pad(t + m * T)];
+    __syncthreads();                              // reads done before the IFFT writes
+    fft_line<N, true>(x, lds, tw, t);
+    store_line<N>(x, out + (size_t)(n + sub) * N, t);
 }
 
 #if SAR_PART == 0
@@ -992,8 +1040,25 @@ static hipError_t launch_line_n(LineOp op, const float2* in, float2* out, int li
         const int groups = (lines + L::LPW - 1) / L::LPW;
         if (groups == 0) return hipSuccess;
         static_assert(L::LDS_BYTES >= RCMC_TAB * (int)sizeof(float), "table fits the line LDS");
-        // variant bit 1: one output row per line slot instead of two
-        if (taps == 8 && ra->stretch_max < 0.5 && (lines & 1) == 0 && !(variant & 2)) {
+        // variant bit 1: one output row per line slot instead of two; bit 2
+        // (FP32, N = 4096 or 8192): the two rows on two line slots' threads
+        // (k_rcmc_az2w) instead of one's
+        const bool two_rows = taps == 8 && ra->stretch_max < 0.5 && (lines & 1) == 0 && !(variant & 2);
+        if constexpr (PREC == PREC_FP32 && (N == 4096 || N == 8192)) {
+            if (two_rows && (variant & 4)) {
+                constexpr int lds2 = 2 * LineGeom<N>::LDS * (int)sizeof(float2);
+                static const hipError_t wa =
+                    lds2 <= 64 * 1024 ? hipSuccess
+                                      : hipFuncSetAttribute((const void*)k_rcmc_az2w<N>,
+                                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                            lds2);
+                if (wa != hipSuccess) return wa;
+                hipLaunchKernelGGL((k_rcmc_az2w<N>), dim3(lines / 2), dim3(2 * LineGeom<N>::T), lds2,
+                                   s, in, out, *ra, tw);
+                return hipGetLastError();
+            }
+        }
+        if (two_rows) {
             const int g2 = (lines / 2 + L::LPW - 1) / L::LPW;
             hipLaunchKernelGGL((k_rcmc_az2<N, PREC>), dim3(g2), dim3(L::BLOCK), L::LDS_BYTES, s, in,
                                out, *ra, tw);

@@ -5,7 +5,8 @@
 //       products of two table loads per radix-16 pass, or read from the table
 //       (FP32 butterflies only; the MFMA variants share one scheme);
 //   RCMC + azimuth kernel: the same twiddle choice for its IFFT, and two
-//       output rows per line slot (shared interpolation gathers) or one;
+//       output rows per workgroup (shared interpolation gathers; on one or
+//       on two line slots' threads) or one row;
 //   batched fused line kernel: twiddles and the grid (one workgroup per line
 //       group, or a persistent grid of 1x, 2x or 4x the resident workgroups).
 // Every candidate computes the same result (they differ in instruction mix and
@@ -56,7 +57,7 @@ bool valid_variant(int kind, int v)
     case sar::TK_FUSED:
     case sar::TK_FWD:
     case sar::TK_INV: return v == 0 || v == 1;
-    case sar::TK_RCMC: return v >= 0 && v <= 3;
+    case sar::TK_RCMC: return v >= 0 && v <= 7;
     case sar::TK_BATCH_FUSED: return v >= 0 && v <= 15 && (v & 2) == 0;
     default: return false;
     }
@@ -407,8 +408,11 @@ sar_status sar_autotune(const sar_params* p, const char* cache_path)
         if (st == SAR_OK && fused) {
             const sar::RcmcHost rh = sar::plan_rcmc(P);
             std::vector<Candidate> cs;
-            for (int v = 0; v < 4; ++v)
-                if (fp32 || !(v & 1)) cs.push_back({v, 0.f});
+            for (int v = 0; v < 8; ++v) {
+                if (!fp32 && (v & 5)) continue;           // table twiddles / wide: FP32 only
+                if ((v & 4) && ((v & 2) || (Na != 4096 && Na != 8192))) continue;   // no effect
+                cs.push_back({v, 0.f});
+            }
             st = time_candidates(
                 cs,
                 [&](int v) {

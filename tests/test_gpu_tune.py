@@ -87,7 +87,7 @@ def test_autotune_writes_cache_and_plans_use_it(tmp_path, name):
     assert rel_l2(img, ref) <= 1e-5
 
 
-@pytest.mark.parametrize("rcmc_variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("rcmc_variant", [0, 1, 2, 3, 4, 5])
 def test_hyperbolic_variants_match_oracle(tmp_path, rcmc_variant):
     cfg, sc, ref = scene("c2")
     base = run(cfg, sc.raw)
