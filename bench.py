@@ -15,7 +15,8 @@ Besides the headline it measures, each on the same GPU:
                 they run on (the slowest kernel carries the roofline figure);
   unfused       the 3-dispatch comparator;
   split         the same scene with radix-16 butterflies on MFMA (split
-                FP16 / BF16 operands, FP32 accumulation);
+                FP16 / BF16 operands, FP32 accumulation), and with FP32
+                arithmetic over FP16 intermediate buffers (fp32_halfstore);
   fft_batched   batched 4096-point line FFTs alone (batch 256 and 4096), FP32
                 and split precisions, in GFLOPS;
   batch         64 scenes of uneven size (LFM, Nr 1024..16384, Na 512..8192)
@@ -195,6 +196,17 @@ def headline(args, torch, sar, cfg, raw, dev):
                               max(10, args.steps // 2), 3)
                 images[prec] = img.cpu().numpy()
             split[prec] = {"ms_per_step": round(ms, 4), "value": round(px / (ms * 1e-3) / 1e6, 1)}
+        # FP32 arithmetic with FP16 intermediate buffers (one exponent per line)
+        with sar.Plan(cfg, precision="fp32_halfstore") as hp:
+            hwork = torch.empty((hp.workspace_bytes + 7) // 8, dtype=torch.complex64, device=dev)
+            ms, _ = timed(lambda: sar.sar_rda_execute(hp.handle, raw, img, hwork, stream),
+                          max(10, args.steps // 2), 3)
+            images["fp32_halfstore"] = img.cpu().numpy()
+            del hwork
+        split["fp32_halfstore"] = {
+            "ms_per_step": round(ms, 4), "value": round(px / (ms * 1e-3) / 1e6, 1),
+            "design_bytes_per_px": 40,
+            "hbm_frac_design": round(40 * px / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     torch.cuda.synchronize()
     plan.close()
     uplan.close()

@@ -58,7 +58,12 @@ typedef enum {
 } sar_status;
 
 typedef enum { SAR_AZ_LFM = 0, SAR_AZ_HYPERBOLIC = 1 } sar_az_model;
-typedef enum { SAR_FP32 = 0, SAR_SPLIT_FP16 = 1, SAR_SPLIT_BF16 = 2 } sar_precision;
+typedef enum {
+    SAR_FP32 = 0,
+    SAR_SPLIT_FP16 = 1,
+    SAR_SPLIT_BF16 = 2,
+    SAR_FP32_HALF_STORAGE = 3
+} sar_precision;
 typedef enum { SAR_FUSED = 0, SAR_UNFUSED = 1 } sar_schedule;
 
 /*
@@ -83,7 +88,19 @@ typedef enum { SAR_FUSED = 0, SAR_UNFUSED = 1 } sar_schedule;
  *  rcmc_taps       0 (no RCMC) or 8: Kaiser-windowed sinc, taps -3..4 about
  *                  floor(p), weights normalised to unit sum; rcmc_beta is the
  *                  Kaiser beta (2.5 by default).
- *  precision       SAR_FP32, or the split-FP16 / split-BF16 MFMA butterflies.
+ *  precision       SAR_FP32, or the split-FP16 / split-BF16 MFMA butterflies,
+ *                  or SAR_FP32_HALF_STORAGE: FP32 arithmetic, but
+ *                  sar_rda_execute keeps its intermediates (range-compressed,
+ *                  turned and range-Doppler data) in the workspace as FP16
+ *                  pairs with one power-of-two exponent per line, chosen so
+ *                  the line's largest component lands in [2^14, 2^15).
+ *                  That moves 40 instead of 64 bytes per pixel, at the
+ *                  precision of two FP16 roundings (the paper's Sec. VI
+ *                  mixed-precision future work).  It needs the fused
+ *                  schedule, transpose_back = 0 and, for the hyperbolic model,
+ *                  8-tap RCMC with stretch < 0.5 (else SAR_ERR_UNSUPPORTED).
+ *                  The individual step functions, which take and return
+ *                  complex64, run as SAR_FP32.
  *  schedule        SAR_FUSED (one kernel per line pass) or SAR_UNFUSED
  *                  (separate FFT, multiply and IFFT dispatches, Sec. II.B
  *                  Fig. 1 top) -- the comparator.
@@ -115,7 +132,9 @@ sar_status sar_plan(const sar_params* p, void* stream, sar_plan_t* out);
 void sar_plan_destroy(sar_plan_t plan);
 
 /* Bytes of device workspace sar_rda_execute / sar_azimuth_compress need:
- * 8 * Na * Nr (one scene-sized complex64 buffer). */
+ * 8 * Na * Nr (one scene-sized complex64 buffer); for SAR_FP32_HALF_STORAGE
+ * two FP16 scene arrays plus 4 * (Na + Nr) bytes of exponents (each block
+ * 256-byte aligned). */
 size_t sar_workspace_bytes(sar_plan_t plan);
 
 /* Range compression (Sec. IV.A step 1): every row of in_dev [Na][Nr] goes

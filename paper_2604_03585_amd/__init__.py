@@ -57,7 +57,8 @@ class Plan:
         if out is None:
             out = torch.empty(self.image_shape(), dtype=torch.complex64, device=raw.device)
         if work is None:
-            work = torch.empty((self.Na * self.Nr,), dtype=torch.complex64, device=raw.device)
+            work = torch.empty(((self.workspace_bytes + 7) // 8,), dtype=torch.complex64,
+                               device=raw.device)
         sar_rda_execute(self.handle, raw, out, work, stream)
         return out
 

@@ -47,7 +47,7 @@ STATUS_NAMES = {0: "SAR_OK", 1: "SAR_ERR_NULL", 2: "SAR_ERR_BAD_SIZE", 3: "SAR_E
                 7: "SAR_ERR_UNSUPPORTED"}
 
 SAR_AZ_LFM, SAR_AZ_HYPERBOLIC = 0, 1
-SAR_FP32, SAR_SPLIT_FP16, SAR_SPLIT_BF16 = 0, 1, 2
+SAR_FP32, SAR_SPLIT_FP16, SAR_SPLIT_BF16, SAR_FP32_HALF_STORAGE = 0, 1, 2, 3
 SAR_FUSED, SAR_UNFUSED = 0, 1
 
 TABLE_HR, TABLE_HA, TABLE_STRETCH, TABLE_RATE, TABLE_RCMC = 0, 1, 2, 3, 4
@@ -160,7 +160,8 @@ def sar_version() -> str:
 
 
 _AZ = {"lfm": SAR_AZ_LFM, "hyperbolic": SAR_AZ_HYPERBOLIC}
-_PREC = {"fp32": SAR_FP32, "split_fp16": SAR_SPLIT_FP16, "split_bf16": SAR_SPLIT_BF16}
+_PREC = {"fp32": SAR_FP32, "split_fp16": SAR_SPLIT_FP16, "split_bf16": SAR_SPLIT_BF16,
+         "fp32_halfstore": SAR_FP32_HALF_STORAGE}
 _SCHED = {"fused": SAR_FUSED, "unfused": SAR_UNFUSED}
 
 

@@ -98,6 +98,30 @@ struct sar_plan_s {
     int var_a[4] = {0, 0, 0, 0};  // ... of the Na line kernels (fused, fwd, inv, RCMC)
 };
 
+namespace {
+// Butterfly precision of the line kernels: half storage computes in FP32.
+int arith(const sar_plan_s* P) { return P->p.precision == SAR_FP32_HALF_STORAGE ? SAR_FP32 : P->p.precision; }
+
+// Workspace layout of a half-storage plan: two FP16 scene arrays, then the
+// per-line exponents of the range lines (Na ints) and of the range-Doppler
+// rows (Nr ints), each block 256-byte aligned.
+struct HalfLayout {
+    size_t wa, wb, e1, e2, total;
+};
+HalfLayout half_layout(int Na, int Nr)
+{
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t px = (size_t)Na * (size_t)Nr;
+    HalfLayout h;
+    h.wa = 0;
+    h.wb = al(4 * px);
+    h.e1 = h.wb + al(4 * px);
+    h.e2 = h.e1 + al(4 * (size_t)Na);
+    h.total = h.e2 + al(4 * (size_t)Nr);
+    return h;
+}
+}  // namespace
+
 namespace sar {
 PlanTables plan_tables(const sar_plan_s* P)
 {
@@ -135,12 +159,22 @@ sar_status validate_params(const sar_params* p)
     } else {
         return fail(SAR_ERR_BAD_PARAM, "az_model=%d unknown", p->az_model);
     }
-    if (p->precision < SAR_FP32 || p->precision > SAR_SPLIT_BF16)
+    if (p->precision < SAR_FP32 || p->precision > SAR_FP32_HALF_STORAGE)
         return fail(SAR_ERR_BAD_PARAM, "precision=%d unknown", p->precision);
     if (p->schedule != SAR_FUSED && p->schedule != SAR_UNFUSED)
         return fail(SAR_ERR_BAD_PARAM, "schedule=%d unknown", p->schedule);
     if (p->transpose_back != 0 && p->transpose_back != 1)
         return fail(SAR_ERR_BAD_PARAM, "transpose_back must be 0 or 1");
+    if (p->precision == SAR_FP32_HALF_STORAGE) {
+        if (p->schedule != SAR_FUSED || p->transpose_back != 0)
+            return fail(SAR_ERR_UNSUPPORTED, "half storage runs the fused schedule without transpose_back");
+        if (p->az_model == SAR_AZ_HYPERBOLIC) {
+            const double x = p->lambda * 0.5 / (2.0 * p->v);
+            const double D = std::sqrt(1.0 - x * x);
+            if (p->rcmc_taps != 8 || !(x * x / (D * (1.0 + D)) < 0.5))
+                return fail(SAR_ERR_UNSUPPORTED, "half storage needs 8-tap RCMC with stretch < 0.5");
+        }
+    }
     return SAR_OK;
 }
 
@@ -193,16 +227,16 @@ sar_status step_range(const sar_plan_s* P, const void* in, void* out, hipStream_
 {
     const int Nr = P->p.Nr, Na = P->p.Na;
     if (P->p.schedule == SAR_FUSED) {
-        HIP_TRY(sar::launch_line(LineOp::Fused, Nr, in, out, Na, P->Hr, P->tw_r, 1.f, nullptr, P->p.precision,
+        HIP_TRY(sar::launch_line(LineOp::Fused, Nr, in, out, Na, P->Hr, P->tw_r, 1.f, nullptr, arith(P),
                                  P->var_r[sar::TK_FUSED], s),
                 "range fused launch");
     } else {
         HIP_TRY(sar::launch_line(LineOp::Forward, Nr, in, out, Na, nullptr, P->tw_r, 1.f, nullptr,
-                                 P->p.precision, P->var_r[sar::TK_FWD], s),
+                                 arith(P), P->var_r[sar::TK_FWD], s),
                 "range FFT launch");
         HIP_TRY(sar::launch_rowmul(out, out, Na, Nr, P->Hr, s), "range multiply launch");
         HIP_TRY(sar::launch_line(LineOp::Inverse, Nr, out, out, Na, nullptr, P->tw_r, 1.f, nullptr,
-                                 P->p.precision, P->var_r[sar::TK_INV], s),
+                                 arith(P), P->var_r[sar::TK_INV], s),
                 "range IFFT launch");
     }
     return SAR_OK;
@@ -221,34 +255,65 @@ sar_status step_azimuth(const sar_plan_s* P, const void* in, void* out, void* wo
     if (P->p.az_model == SAR_AZ_LFM) {
         if (P->p.schedule == SAR_FUSED) {
             HIP_TRY(sar::launch_line(LineOp::Fused, Na, in, out, Nr, P->Ha, P->tw_a, 1.f, nullptr,
-                                     P->p.precision, P->var_a[sar::TK_FUSED], s),
+                                     arith(P), P->var_a[sar::TK_FUSED], s),
                     "azimuth fused launch");
         } else {
             HIP_TRY(sar::launch_line(LineOp::Forward, Na, in, out, Nr, nullptr, P->tw_a, 1.f, nullptr,
-                                     P->p.precision, P->var_a[sar::TK_FWD], s),
+                                     arith(P), P->var_a[sar::TK_FWD], s),
                     "azimuth FFT launch");
             HIP_TRY(sar::launch_rowmul(out, out, Nr, Na, P->Ha, s), "azimuth multiply launch");
             HIP_TRY(sar::launch_line(LineOp::Inverse, Na, out, out, Nr, nullptr, P->tw_a, 1.f, nullptr,
-                                     P->p.precision, P->var_a[sar::TK_INV], s),
+                                     arith(P), P->var_a[sar::TK_INV], s),
                     "azimuth IFFT launch");
         }
         return SAR_OK;
     }
     const sar::RcmcHost rh = rcmc_host(P);
     HIP_TRY(sar::launch_line(LineOp::Forward, Na, in, work, Nr, nullptr, P->tw_a, 1.f, nullptr,
-                             P->p.precision, P->var_a[sar::TK_FWD], s),
+                             arith(P), P->var_a[sar::TK_FWD], s),
             "azimuth FFT launch");
     if (P->p.schedule == SAR_FUSED) {
         HIP_TRY(sar::launch_line(LineOp::RcmcAz, Na, work, out, Nr, nullptr, P->tw_a, 1.f, &rh,
-                                 P->p.precision, P->var_a[sar::TK_RCMC], s),
+                                 arith(P), P->var_a[sar::TK_RCMC], s),
                 "RCMC+azimuth launch");
     } else {
         HIP_TRY(sar::launch_rcmc_interp(work, out, Na, rh, s), "RCMC launch");
         HIP_TRY(sar::launch_az_phase(out, out, Na, rh, 1.0f / (float)Na, s), "azimuth phase launch");
         HIP_TRY(sar::launch_line(LineOp::Inverse, Na, out, out, Nr, nullptr, P->tw_a, 1.f, nullptr,
-                                     P->p.precision, P->var_a[sar::TK_INV], s),
+                                     arith(P), P->var_a[sar::TK_INV], s),
                 "azimuth IFFT launch");
     }
+    return SAR_OK;
+}
+
+// Half storage (fused schedule): the intermediates live in the workspace as
+// FP16 pairs with one power-of-two exponent per line (see half_layout):
+//   range      raw (complex64) -> Wa [Na][Nr] FP16, E1[Na]
+//   turn       Wa -> Wb [Nr][Na] FP16 (4-byte elements; point m keeps E1[m])
+//   LFM:       azimuth FFT*H*IFFT  Wb -> img (complex64)
+//   hyperbolic azimuth FFT  Wb -> Wa [Nr][Na] FP16, E2[Nr];
+//              RCMC + phase + IFFT  Wa -> img (complex64)
+sar_status execute_half(const sar_plan_s* P, const void* raw, void* img, void* work, hipStream_t s)
+{
+    const int Nr = P->p.Nr, Na = P->p.Na;
+    const HalfLayout L = half_layout(Na, Nr);
+    char* w = (char*)work;
+    void* Wa = w + L.wa;
+    void* Wb = w + L.wb;
+    int* E1 = (int*)(w + L.e1);
+    int* E2 = (int*)(w + L.e2);
+    HIP_TRY(sar::launch_line_half(sar::HalfOp::RangeFused, Nr, raw, Wa, Na, P->Hr, P->tw_r, nullptr, E1, s),
+            "range launch (half storage)");
+    HIP_TRY(sar::launch_corner_turn_b4(Wa, Wb, Na, Nr, s), "corner turn launch (half storage)");
+    if (P->p.az_model == SAR_AZ_LFM) {
+        HIP_TRY(sar::launch_line_half(sar::HalfOp::AzimuthFused, Na, Wb, img, Nr, P->Ha, P->tw_a, E1, nullptr,
+                                      s),
+                "azimuth launch (half storage)");
+        return SAR_OK;
+    }
+    HIP_TRY(sar::launch_line_half(sar::HalfOp::AzimuthForward, Na, Wb, Wa, Nr, nullptr, P->tw_a, E1, E2, s),
+            "azimuth FFT launch (half storage)");
+    HIP_TRY(sar::launch_rcmc_half(Na, Wa, E2, img, rcmc_host(P), P->tw_a, s), "RCMC launch (half storage)");
     return SAR_OK;
 }
 
@@ -283,8 +348,9 @@ sar_status sar_plan(const sar_params* p, void* stream, sar_plan_t* out)
     const int Nr = p->Nr, Na = p->Na;
     const bool hyper = p->az_model == SAR_AZ_HYPERBOLIC;
     sar::load_tune_cache_once();
-    for (int k = 0; k < 3; ++k) P->var_r[k] = sar::tuned_variant(k, Nr, p->precision);
-    for (int k = 0; k < 4; ++k) P->var_a[k] = sar::tuned_variant(k, Na, p->precision);
+    const int ap = p->precision == SAR_FP32_HALF_STORAGE ? SAR_FP32 : p->precision;
+    for (int k = 0; k < 3; ++k) P->var_r[k] = sar::tuned_variant(k, Nr, ap);
+    for (int k = 0; k < 4; ++k) P->var_a[k] = sar::tuned_variant(k, Na, ap);
     const size_t A = 256;
     size_t off = 0;
     const size_t o_twr = off; off = align_up(off + sizeof(float2) * (size_t)sar::twiddle_table_size(Nr), A);
@@ -346,7 +412,12 @@ void sar_plan_destroy(sar_plan_t plan)
     delete plan;
 }
 
-size_t sar_workspace_bytes(sar_plan_t plan) { return plan ? scene_bytes(plan) : 0; }
+size_t sar_workspace_bytes(sar_plan_t plan)
+{
+    if (!plan) return 0;
+    if (plan->p.precision == SAR_FP32_HALF_STORAGE) return half_layout(plan->p.Na, plan->p.Nr).total;
+    return scene_bytes(plan);
+}
 
 sar_status sar_range_compress(sar_plan_t P, const void* in, void* out, void* stream)
 {
@@ -395,10 +466,11 @@ sar_status sar_rda_execute(sar_plan_t P, const void* raw, void* img, void* work,
     if ((st = check_plan(P)) || (st = check_ptr(raw, "raw")) || (st = check_ptr(img, "img")) ||
         (st = check_ptr(work, "work")))
         return st;
-    const size_t n = scene_bytes(P);
-    if (overlap(raw, n, img, n) || overlap(raw, n, work, n) || overlap(img, n, work, n))
+    const size_t n = scene_bytes(P), nw = sar_workspace_bytes(P);
+    if (overlap(raw, n, img, n) || overlap(raw, n, work, nw) || overlap(img, n, work, nw))
         return fail(SAR_ERR_ALIAS, "raw, img and work must be pairwise disjoint");
     hipStream_t s = (hipStream_t)stream;
+    if (P->p.precision == SAR_FP32_HALF_STORAGE) return execute_half(P, raw, img, work, s);
     const int Nr = P->p.Nr, Na = P->p.Na;
     const bool back = P->p.transpose_back != 0;
     // Buffers alternate so that the last step writes img.
@@ -434,7 +506,7 @@ sar_status sar_fft_lines(sar_plan_t P, int32_t axis, int32_t inverse, const void
     if (in != out && overlap(in, n, out, n)) return fail(SAR_ERR_ALIAS, "in and out partially overlap");
     HIP_TRY(sar::launch_line(inverse ? LineOp::Inverse : LineOp::Forward, N, in, out, lines, nullptr,
                              axis == 0 ? P->tw_r : P->tw_a, inverse ? 1.0f / (float)N : 1.0f, nullptr,
-                             P->p.precision, (axis == 0 ? P->var_r : P->var_a)[inverse ? sar::TK_INV : sar::TK_FWD],
+                             arith(P), (axis == 0 ? P->var_r : P->var_a)[inverse ? sar::TK_INV : sar::TK_FWD],
                              (hipStream_t)stream),
             "FFT launch");
     return SAR_OK;
@@ -462,13 +534,13 @@ sar_status sar_rcmc_azimuth(sar_plan_t P, const void* A, void* out, void* stream
     hipStream_t s = (hipStream_t)stream;
     if (P->p.schedule == SAR_FUSED) {
         HIP_TRY(sar::launch_line(LineOp::RcmcAz, P->p.Na, A, out, P->p.Nr, nullptr, P->tw_a, 1.f, &rh,
-                                 P->p.precision, P->var_a[sar::TK_RCMC], s),
+                                 arith(P), P->var_a[sar::TK_RCMC], s),
                 "RCMC+azimuth launch");
     } else {
         HIP_TRY(sar::launch_rcmc_interp(A, out, P->p.Na, rh, s), "RCMC launch");
         HIP_TRY(sar::launch_az_phase(out, out, P->p.Na, rh, 1.0f / (float)P->p.Na, s), "phase launch");
         HIP_TRY(sar::launch_line(LineOp::Inverse, P->p.Na, out, out, P->p.Nr, nullptr, P->tw_a, 1.f,
-                                 nullptr, P->p.precision, P->var_a[sar::TK_INV], s),
+                                 nullptr, arith(P), P->var_a[sar::TK_INV], s),
                 "azimuth IFFT launch");
     }
     return SAR_OK;

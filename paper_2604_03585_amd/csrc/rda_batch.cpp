@@ -10,8 +10,8 @@
 // buffer pointers rebuilds the tasks and the graph.
 //
 // Scenes whose processing the batched launches do not cover (hyperbolic
-// azimuth, the unfused schedule) run through sar_rda_execute inside the same
-// stream (and graph).
+// azimuth, the unfused schedule, half storage) run through sar_rda_execute
+// inside the same stream (and graph).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -83,7 +83,7 @@ void drop_graph(sar_batch_s* B)
 
 bool batched(const sar_params& p)
 {
-    return p.az_model == SAR_AZ_LFM && p.schedule == SAR_FUSED;
+    return p.az_model == SAR_AZ_LFM && p.schedule == SAR_FUSED && p.precision != SAR_FP32_HALF_STORAGE;
 }
 
 // Build task arrays for this buffer set and upload them (synchronous).

@@ -77,6 +77,21 @@ enum TuneKind { TK_FUSED = 0, TK_FWD = 1, TK_INV = 2, TK_RCMC = 3, TK_BATCH_FUSE
 int tuned_variant(int kind, int n, int prec);
 void load_tune_cache_once();
 
+// Half storage (FP32 arithmetic, FP16 intermediates with a power-of-two
+// scale per line; see k_line_hs):
+//  RangeFused:     complex64 lines -> FP16 lines, ex_out[line] exponents
+//  AzimuthFused:   FP16 lines (point j scaled by 2^ex_in[j]) -> complex64
+//  AzimuthForward: FP16 lines (as above) -> FFT -> FP16 lines + ex_out
+enum class HalfOp { RangeFused, AzimuthFused, AzimuthForward };
+hipError_t launch_line_half(HalfOp op, int n, const void* in, void* out, int lines, const void* H,
+                            const void* tw, const int* ex_in, int* ex_out, hipStream_t s);
+// Two-row RCMC + azimuth from FP16 range-Doppler rows (row r scaled by
+// 2^ex[r]) into complex64 (requires taps == 8, stretch_max < 0.5, even nr).
+hipError_t launch_rcmc_half(int n, const void* A, const int* ex, void* out, const RcmcHost& rh,
+                            const void* tw, hipStream_t s);
+// Corner turn of 4-byte elements (FP16 pairs); rows, cols multiples of 64.
+hipError_t launch_corner_turn_b4(const void* in, void* out, int rows, int cols, hipStream_t s);
+
 hipError_t launch_corner_turn_batch(const void* tasks, int ntasks, int total_tiles, hipStream_t s);
 int line_groups(int n, int lines);        // line groups of `lines` lines of length n
 

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "fft_line.hpp"
 #include "mfma_fft.hpp"
@@ -95,6 +96,14 @@ __global__ void k_gen_chirp_filter(float2* __restrict__ H, int n, int len, doubl
 #endif  // SAR_PART == 0
 
 // ===================================================== line kernels
+// FP16 storage of intermediates (the half-storage precision mode): a
+// complex sample as two _Float16, with a power-of-two scale per line.
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float2 h2_to_f2(h2_t v, float scale)
+{
+    return make_float2((float)v.x * scale, (float)v.y * scale);
+}
 template <int N> struct LineLaunch {
     static constexpr int T = LineGeom<N>::T;
     static constexpr int LPW = T >= 256 ? 1 : 256 / T;     // lines per workgroup
@@ -327,6 +336,32 @@ __global__ __launch_bounds__(256) void k_corner_turn_x2(const float4* __restrict
     }
 }
 
+// k_corner_turn_x2 for 4-byte elements (FP16 pairs): whole 64 x 64 tiles,
+// every global access moves two elements (8 bytes).
+__global__ __launch_bounds__(256) void k_corner_turn_b4(const uint2* __restrict__ in,
+                                                        uint2* __restrict__ out, int rows, int cols)
+{
+    __shared__ uint32_t tile[TT][TT + 1];
+    const int tiles_c = cols / TT;
+    const int tr = blockIdx.x / tiles_c, tc = blockIdx.x % tiles_c;
+    const int r0 = tr * TT, c0 = tc * TT;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int cols2 = cols / 2, rows2 = rows / 2;
+#pragma unroll
+    for (int i = 0; i < TT / 8; ++i) {
+        const int r = ty + 8 * i;
+        const uint2 v = in[(size_t)(r0 + r) * cols2 + c0 / 2 + tx];
+        tile[r][2 * tx] = v.x;
+        tile[r][2 * tx + 1] = v.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < TT / 8; ++i) {
+        const int c = ty + 8 * i;
+        out[(size_t)(c0 + c) * rows2 + r0 / 2 + tx] = make_uint2(tile[2 * tx][c], tile[2 * tx + 1][c]);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_corner_turn_batch(const TurnTask* __restrict__ tasks,
                                                            int ntasks, int total_tiles)
 {
@@ -461,6 +496,7 @@ struct RcmcArgs {
     double x_per_bin;        // lambda / (2 v Na): x_k = signed bin * x_per_bin
     double two_over_lam;     // 2 / lambda
     int nr;
+    const int* row_exp;      // half storage: per-row exponents of the FP16 input
 };
 
 // The per-bin geometry from the bin index: f_k in fftfreq order,
@@ -735,6 +771,27 @@ k_rcmc_az(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
 // cover both: 10 gathers for 2 samples instead of 16.  The per-bin
 // geometry is computed, not loaded, so the gathers of the next column can be
 // issued before the current column is combined without a load-to-load chain.
+// Range-Doppler rows stored as FP16 pairs, row r scaled by 2^-ex[r].
+struct HalfRows {
+    const h2_t* a;
+    const int* ex;
+};
+
+template <int N, bool EDGE>
+__device__ __forceinline__ void rcmc_gather10(float2 (&w)[10], const HalfRows& A, int k, int i0,
+                                              int nr)
+{
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const int r = i0 - 3 + i;
+        const int rc = EDGE ? min(max(r, 0), nr - 1) : r;
+        const h2_t v = *(const h2_t*)((const char*)A.a + ((uint32_t)rc * (uint32_t)N + (uint32_t)k) * 4u);
+        const float2 f = h2_to_f2(v, ldexpf(1.0f, A.ex[rc]));
+        const bool in = !EDGE || ((r >= 0) & (r < nr));
+        w[i] = make_float2(in ? f.x : 0.f, in ? f.y : 0.f);
+    }
+}
+
 template <int N, bool EDGE>
 __device__ __forceinline__ void rcmc_gather10(float2 (&w)[10], const float2* __restrict__ A,
                                               int k, int i0, int nr)
@@ -800,11 +857,11 @@ __device__ __forceinline__ void rcmc_pair_combine(float2& ya, float2& yb, const 
     yb = c_mul(rcmc_combine(c.xb, tab, tb), c.pb);
 }
 
-// Columns t + m * S (m < C) of rows n, n+1.
-template <int N, bool EDGE, int C = line_e(N), int S = LineGeom<N>::T>
-__device__ __forceinline__ void rcmc_rows2(float2 (&xa)[C], float2 (&xb)[C],
-                                           const float2* __restrict__ A, const RcmcArgs& ra,
-                                           int n, int t, const float* __restrict__ tab)
+// Columns t + m * S (m < C) of rows n, n+1 of A (FP32 rows, or HalfRows).
+template <int N, bool EDGE, int C = line_e(N), int S = LineGeom<N>::T, class Src = const float2*>
+__device__ __forceinline__ void rcmc_rows2(float2 (&xa)[C], float2 (&xb)[C], Src A,
+                                           const RcmcArgs& ra, int n, int t,
+                                           const float* __restrict__ tab)
 {
     constexpr int T = S;
     constexpr int E = C;
@@ -831,11 +888,16 @@ __device__ __forceinline__ void rcmc_rows2(float2 (&xa)[C], float2 (&xb)[C],
     }
 }
 
-template <int N, int PREC>
+// HIN: A holds FP16 rows with per-row exponents ra.row_exp (half storage).
+template <int N, int PREC, bool HIN = false>
 __global__ __launch_bounds__(LineLaunch<N>::BLOCK) void
-k_rcmc_az2(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
+k_rcmc_az2(const void* __restrict__ A_, float2* __restrict__ out, RcmcArgs ra,
            const float2* __restrict__ tw)
 {
+    using SrcT = typename std::conditional<HIN, HalfRows, const float2*>::type;
+    SrcT A;
+    if constexpr (HIN) A = HalfRows{(const h2_t*)A_, ra.row_exp};
+    else A = (const float2*)A_;
     using L = LineLaunch<N>;
     constexpr int E = line_e(N);
     extern __shared__ __align__(16) float2 smem[];
@@ -857,9 +919,9 @@ k_rcmc_az2(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
     } else {
         const double smax = (ra.r_near + (double)n + 1.0) * ra.stretch_max;
         if (n >= 3 && (double)n + 1.0 + smax + 6.0 <= (double)(ra.nr - 1))
-            rcmc_rows2<N, false>(xa, xb, A, ra, n, t, tab);
+            rcmc_rows2<N, false, line_e(N), LineGeom<N>::T, SrcT>(xa, xb, A, ra, n, t, tab);
         else
-            rcmc_rows2<N, true>(xa, xb, A, ra, n, t, tab);
+            rcmc_rows2<N, true, line_e(N), LineGeom<N>::T, SrcT>(xa, xb, A, ra, n, t, tab);
     }
     __syncthreads();                              // table reads done before LDS reuse
     fft_any<N, true, PREC>(xa, lds, tw, sub, t);
@@ -948,6 +1010,117 @@ __global__ __launch_bounds__(256) void k_az_phase(const float2* __restrict__ in,
 }
 
 #endif  // SAR_PART == 0
+
+#if SAR_PART == 1
+// ===================================================== half storage (FP32 math)
+// Largest |re|, |im| of one line's samples (the line's T threads: aligned
+// lane segments of a wave when T < 64, else whole waves combined through
+// `scratch`, 16 floats of LDS that no thread still reads).
+template <int N>
+__device__ __forceinline__ float line_absmax(const float2 (&x)[line_e(N)], float* scratch, int sub)
+{
+    using L = LineLaunch<N>;
+    float m = 0.f;
+#pragma unroll
+    for (int i = 0; i < line_e(N); ++i) m = fmaxf(m, fmaxf(fabsf(x[i].x), fabsf(x[i].y)));
+    constexpr int W = L::T < 64 ? L::T : 64;
+#pragma unroll
+    for (int off = 1; off < W; off <<= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if constexpr (L::T > 64) {
+        constexpr int WPL = L::T / 64;            // waves per line
+        static_assert(L::BLOCK / 64 <= 16, "scratch holds one float per wave");
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        __syncthreads();
+        if (lane == 0) scratch[wave] = m;
+        __syncthreads();
+        m = 0.f;
+#pragma unroll
+        for (int w = 0; w < WPL; ++w) m = fmaxf(m, scratch[sub * WPL + w]);
+    }
+    return m;
+}
+
+// Exponent e of a line whose largest component is amax: the stored values
+// x * 2^-e have their largest component in [2^14, 2^15) (FP16 holds up to
+// 65504); empty, non-finite or all-zero lines keep e = 0.
+__device__ __forceinline__ int half_exponent(float amax)
+{
+    if (!(amax > 0.f) || !(amax < INFINITY)) return 0;
+    return max(ilogbf(amax) - 14, -100);
+}
+
+// FP32 line transform with FP16 storage on either side.
+//  IN_H:  `in` holds lines of FP16 pairs; point j of every line carries the
+//         scale 2^ex_in[j] (the exponent of the range line the point came
+//         from, after the corner turn);
+//  OUT_H: `out` receives FP16 pairs x * 2^-e, e = ex_out[line] chosen per
+//         line by half_exponent; else `out` is complex64.
+template <int N, int KIND, bool IN_H, bool OUT_H>
+__global__ __launch_bounds__(LineLaunch<N>::BLOCK)
+__attribute__((amdgpu_waves_per_eu(line_wpe<N, PREC_FP32>()))) void
+k_line_hs(const void* __restrict__ in, void* __restrict__ out, int lines,
+          const float2* __restrict__ H, const float2* __restrict__ tw,
+          const int* __restrict__ ex_in, int* __restrict__ ex_out)
+{
+    using L = LineLaunch<N>;
+    constexpr int E = line_e(N);
+    extern __shared__ __align__(16) float2 smem[];
+    const int groups = (lines + L::LPW - 1) / L::LPW;
+    const int g = xcd_group(blockIdx.x, groups);
+    const int sub = threadIdx.x / L::T, t = threadIdx.x % L::T;
+    const int line = g * L::LPW + sub;
+    const bool live = line < lines;
+    float2* lds = smem + sub * LineGeom<N>::LDS;
+    float2 x[E];
+    if (live) {
+        if constexpr (IN_H) {
+            const h2_t* src = (const h2_t*)in + (size_t)line * N;
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int j = t + m * L::T;
+                x[m] = h2_to_f2(src[j], ldexpf(1.0f, ex_in[j]));
+            }
+        } else {
+            load_line<N>(x, (const float2*)in + (size_t)line * N, t);
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < E; ++m) x[m] = make_float2(0.f, 0.f);
+    }
+    if constexpr (KIND == LK_FUSED) {
+        float2 h[E];
+        fft_line<N, false>(x, lds, tw, t, [&] {
+#pragma unroll
+            for (int m = 0; m < E; ++m) h[m] = H[t + m * L::T];
+        });
+#pragma unroll
+        for (int m = 0; m < E; ++m) x[m] = c_mul(x[m], h[m]);
+        int ti = t;
+        if constexpr (L::RECOMPUTE_INV_TW) asm volatile("" : "+v"(ti));
+        fft_line<N, true>(x, lds, tw, ti);
+    } else {
+        static_assert(KIND == LK_FWD, "fused or forward");
+        fft_line<N, false>(x, lds, tw, t);
+    }
+    if constexpr (OUT_H) {
+        const int e = half_exponent(line_absmax<N>(x, (float*)smem, sub));
+        const float sc = ldexpf(1.0f, -e);
+        if (live) {
+            h2_t* dst = (h2_t*)out + (size_t)line * N;
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                h2_t v;
+                v.x = (_Float16)(x[m].x * sc);
+                v.y = (_Float16)(x[m].y * sc);
+                dst[t + m * L::T] = v;
+            }
+            if (t == 0) ex_out[line] = e;
+        }
+    } else if (live) {
+        store_line<N>(x, (float2*)out + (size_t)line * N, t);
+    }
+}
+#endif  // SAR_PART == 1
 
 // ===================================================== launchers
 static RcmcArgs make_rcmc_args(const RcmcHost& rh)
@@ -1194,6 +1367,104 @@ hipError_t launch_line_fp32(LineOp op, int n, const float2* i, float2* o, int li
 {
     return launch_line_prec<PREC_FP32>(op, n, i, o, lines, h, w, scale, ra, taps, v, s);
 }
+
+template <const void* (*KERNEL)(), int BYTES>
+static hipError_t allow_lds()
+{
+    static const hipError_t e =
+        BYTES <= 64 * 1024
+            ? hipSuccess
+            : hipFuncSetAttribute(KERNEL(), hipFuncAttributeMaxDynamicSharedMemorySize, BYTES);
+    return e;
+}
+
+template <int N, int KIND, bool IN_H, bool OUT_H>
+static const void* hs_kernel() { return (const void*)k_line_hs<N, KIND, IN_H, OUT_H>; }
+
+template <int N, int KIND, bool IN_H, bool OUT_H>
+static hipError_t launch_hs_n(const void* in, void* out, int lines, const void* H, const void* tw,
+                              const int* ex_in, int* ex_out, hipStream_t s)
+{
+    using L = LineLaunch<N>;
+    const hipError_t attr = allow_lds<hs_kernel<N, KIND, IN_H, OUT_H>, L::LDS_BYTES>();
+    if (attr != hipSuccess) return attr;
+    const int groups = (lines + L::LPW - 1) / L::LPW;
+    if (groups == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_line_hs<N, KIND, IN_H, OUT_H>), dim3(groups), dim3(L::BLOCK),
+                       L::LDS_BYTES, s, in, out, lines, (const float2*)H, (const float2*)tw, ex_in,
+                       ex_out);
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_hs_op(HalfOp op, const void* in, void* out, int lines, const void* H,
+                               const void* tw, const int* ex_in, int* ex_out, hipStream_t s)
+{
+    switch (op) {
+    case HalfOp::RangeFused:
+        return launch_hs_n<N, LK_FUSED, false, true>(in, out, lines, H, tw, ex_in, ex_out, s);
+    case HalfOp::AzimuthFused:
+        return launch_hs_n<N, LK_FUSED, true, false>(in, out, lines, H, tw, ex_in, ex_out, s);
+    case HalfOp::AzimuthForward:
+        return launch_hs_n<N, LK_FWD, true, true>(in, out, lines, H, tw, ex_in, ex_out, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_line_half(HalfOp op, int n, const void* in, void* out, int lines, const void* H,
+                            const void* tw, const int* ex_in, int* ex_out, hipStream_t s)
+{
+    switch (n) {
+    case 64: return launch_hs_op<64>(op, in, out, lines, H, tw, ex_in, ex_out, s);
+    case 128: return launch_hs_op<128>(op, in, out, lines, H, tw, ex_in, ex_out, s);
+    case 256: return launch_hs_op<256>(op, in, out, lines, H, tw, ex_in, ex_out, s);
+    case 512: return launch_hs_op<512>(op, in, out, lines, H, tw, ex_in, ex_out, s);
+    case 1024: return launch_hs_op<1024>(op, in, out, lines, H, tw, ex_in, ex_out, s);
+    case 2048: return launch_hs_op<2048>(op, in, out, lines, H, tw, ex_in, ex_out, s);
+    case 4096: return launch_hs_op<4096>(op, in, out, lines, H, tw, ex_in, ex_out, s);
+    case 8192: return launch_hs_op<8192>(op, in, out, lines, H, tw, ex_in, ex_out, s);
+    case 16384: return launch_hs_op<16384>(op, in, out, lines, H, tw, ex_in, ex_out, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int N>
+static const void* rcmc_half_kernel() { return (const void*)k_rcmc_az2<N, PREC_FP32, true>; }
+
+template <int N>
+static hipError_t launch_rcmc_half_n(const void* A, const int* ex, void* out, const RcmcArgs& ra0,
+                                     const void* tw, hipStream_t s)
+{
+    using L = LineLaunch<N>;
+    const hipError_t attr = allow_lds<rcmc_half_kernel<N>, L::LDS_BYTES>();
+    if (attr != hipSuccess) return attr;
+    RcmcArgs ra = ra0;
+    ra.row_exp = ex;
+    const int g2 = (ra.nr / 2 + L::LPW - 1) / L::LPW;
+    if (g2 == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_rcmc_az2<N, PREC_FP32, true>), dim3(g2), dim3(L::BLOCK), L::LDS_BYTES, s,
+                       A, (float2*)out, ra, (const float2*)tw);
+    return hipGetLastError();
+}
+
+hipError_t launch_rcmc_half(int n, const void* A, const int* ex, void* out, const RcmcHost& rh,
+                            const void* tw, hipStream_t s)
+{
+    if (rh.taps != 8 || !(rh.stretch_max < 0.5) || (rh.nr & 1)) return hipErrorInvalidValue;
+    const RcmcArgs ra = make_rcmc_args(rh);
+    switch (n) {
+    case 64: return launch_rcmc_half_n<64>(A, ex, out, ra, tw, s);
+    case 128: return launch_rcmc_half_n<128>(A, ex, out, ra, tw, s);
+    case 256: return launch_rcmc_half_n<256>(A, ex, out, ra, tw, s);
+    case 512: return launch_rcmc_half_n<512>(A, ex, out, ra, tw, s);
+    case 1024: return launch_rcmc_half_n<1024>(A, ex, out, ra, tw, s);
+    case 2048: return launch_rcmc_half_n<2048>(A, ex, out, ra, tw, s);
+    case 4096: return launch_rcmc_half_n<4096>(A, ex, out, ra, tw, s);
+    case 8192: return launch_rcmc_half_n<8192>(A, ex, out, ra, tw, s);
+    case 16384: return launch_rcmc_half_n<16384>(A, ex, out, ra, tw, s);
+    default: return hipErrorInvalidValue;
+    }
+}
 #elif SAR_PART == 2
 hipError_t launch_line_f16(LineOp op, int n, const float2* i, float2* o, int lines,
                            const float2* h, const float2* w, float scale, const RcmcArgs* ra,
@@ -1284,6 +1555,17 @@ hipError_t launch_rowmul(const void* in, void* out, int rows, int n, const void*
     const long long pairs = (long long)rows * n / 2;
     hipLaunchKernelGGL(k_rowmul, dim3(grid_for(pairs, 256)), dim3(256), 0, s, (const float4*)in,
                        (float4*)out, pairs, n, (const float2*)H);
+    return hipGetLastError();
+}
+
+hipError_t launch_corner_turn_b4(const void* in, void* out, int rows, int cols, hipStream_t s)
+{
+    if (rows % TT != 0 || cols % TT != 0 || (((uintptr_t)in | (uintptr_t)out) & 7u) != 0)
+        return hipErrorInvalidValue;
+    const long long tiles = (long long)(rows / TT) * (cols / TT);
+    if (tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_corner_turn_b4, dim3((unsigned)tiles), dim3(256), 0, s, (const uint2*)in,
+                       (uint2*)out, rows, cols);
     return hipGetLastError();
 }
 

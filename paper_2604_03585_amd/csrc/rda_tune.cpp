@@ -329,7 +329,9 @@ sar_status sar_autotune(const sar_params* p, const char* cache_path)
         sar_plan_destroy(P);
         return st;
     }
-    const int Nr = p->Nr, Na = p->Na, prec = p->precision;
+    // half storage computes in FP32: its line kernels are tuned as FP32
+    const int Nr = p->Nr, Na = p->Na,
+              prec = p->precision == SAR_FP32_HALF_STORAGE ? SAR_FP32 : p->precision;
     const bool fp32 = prec == SAR_FP32;
     const bool hyper = p->az_model == SAR_AZ_HYPERBOLIC;
     const bool fused = p->schedule == SAR_FUSED;

@@ -137,9 +137,12 @@ class Arena:
 
 def scene_blocks(cfg: dict) -> tuple[int, int]:
     """(image bytes, scratch bytes) of a request: complex64 image; staging
-    copy of the raw scene plus the workspace."""
-    px = int(cfg["Na"]) * int(cfg["Nr"])
-    return 8 * px, 16 * px
+    copy of the raw scene plus the workspace (one complex64 scene, or for
+    half storage two FP16 scenes and 4 (Na + Nr) bytes of exponents, each
+    block 256-byte aligned)."""
+    na, nr = int(cfg["Na"]), int(cfg["Nr"])
+    px = na * nr
+    return 8 * px, 16 * px + 4 * (na + nr) + 1024
 
 
 def footprint_bytes(cfg: dict) -> int:
@@ -420,7 +423,7 @@ class GpuExecutor:
         px = p.Na * p.Nr
         img = self._view(req.img_off, p.image_shape())
         raw = self._view(req.scratch_off, (p.Na, p.Nr))
-        work = self._view(req.scratch_off + 8 * px, (px,))
+        work = self._view(req.scratch_off + 8 * px, ((p.workspace_bytes + 7) // 8,))
         with self.torch.cuda.stream(s):
             raw.copy_(req.raw, non_blocking=True)       # stage into the request's buffer
             sar_rda_execute(p.handle, raw, img, work, s)

@@ -66,6 +66,24 @@ def test_plan_rejects_bad_enums_and_struct_size():
     assert _status(sar.make_params(config("c1"), precision=9)) == _lib.SAR_ERR_BAD_PARAM
 
 
+@pytest.mark.parametrize("scene, kw", [
+    ("c1", dict(schedule="unfused")),
+    ("c1", dict(transpose_back=1)),
+    ("c2", dict(schedule="unfused")),
+    ("c2", dict(rcmc_taps=0)),
+    ("c2", dict(lam=3.2, v=1.0)),        # stretch 0.67: the 8-row RCMC window cannot hold it
+])
+def test_half_storage_rejects_what_it_does_not_implement(scene, kw):
+    plan_kw = {k: kw.pop(k) for k in ("schedule", "transpose_back") if k in kw}
+    p = sar.make_params(config(scene, **kw), precision="fp32_halfstore", **plan_kw)
+    assert _status(p) == _lib.SAR_ERR_UNSUPPORTED
+
+
+def test_half_storage_bad_enums_stay_bad_param():
+    p = sar.make_params(config("c1"), precision="fp32_halfstore", schedule=5)
+    assert _status(p) == _lib.SAR_ERR_BAD_PARAM
+
+
 def test_null_arguments():
     h = ctypes.c_void_p()
     assert _lib._sar_plan(None, None, ctypes.byref(h)) == _lib.SAR_ERR_NULL

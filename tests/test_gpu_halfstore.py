@@ -1,0 +1,193 @@
+"""Half-precision storage (precision "fp32_halfstore"): every line is
+computed in FP32 as in the FP32 path, but the intermediate scene buffers
+between the kernels hold FP16 pairs with one power-of-two exponent per line.
+
+Stated accuracy: FP16 keeps 11 significand bits, so each stored component
+carries a relative error of at most 2^-11 (4.9e-4) while the per-line
+exponent keeps every line inside FP16's normal range.  The LFM path stores
+the scene once (range output), the hyperbolic path twice (range output and
+azimuth spectrum), so the image is held to 2e-3 relative L2 against the FP64
+oracle (two roundings plus at most 2x growth through the compression
+filters); the peak cells must equal the oracle's and the seeded cells,
+|dPSLR|, |dISLR| <= 0.1 dB and |dSNR| <= 0.05 dB as for FP32.
+"""
+import numpy as np
+import pytest
+
+import paper_2604_03585_amd as sar
+from gpu_util import dev, empty, host, rel_l2, torch_cuda
+from oracle import oracle as O
+from oracle import quality as Q
+from sarsim import config, simulate
+
+pytestmark = pytest.mark.gpu
+
+PREC = "fp32_halfstore"
+TOL_HALF = 2e-3
+
+_cache = {}
+
+
+def scene_and_oracle(name, **over):
+    key = (name, tuple(sorted(over.items())))
+    if key not in _cache:
+        cfg = config(name, **over)
+        sc = simulate(cfg)
+        _cache[key] = (cfg, sc, O.rda(sc.raw, cfg))
+    return _cache[key]
+
+
+def run(cfg, raw, precision=PREC):
+    with sar.Plan(cfg, precision=precision) as p:
+        return host(p.execute(dev(raw))).T
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_halfstore_rda_against_oracle(name):
+    cfg, sc, ref = scene_and_oracle(name)
+    img = run(cfg, sc.raw)
+    err = rel_l2(img, ref)
+    guard, half = (16, 32) if cfg["Nr"] <= 256 else (64, 64)
+    rg = Q.point_target_report(img, sc.targets, guard, half)
+    ro = Q.point_target_report(ref, sc.targets, guard, half)
+    d = {k: max(abs(a[k] - b[k]) for a, b in zip(rg, ro))
+         for k in ("snr_db", "pslr_range", "islr_range", "pslr_azimuth", "islr_azimuth")}
+    print(f"halfstore {name}: rel L2 {err:.3e} max abs {Q.max_abs(img, ref):.3e} "
+          + " ".join(f"d{k}={v:.4f}" for k, v in d.items()))
+    assert err <= TOL_HALF
+    for t, a, b in zip(sc.targets, rg, ro):
+        assert a["peak"] == b["peak"] == (t["m"], t["n"])
+        for key in ("pslr_range", "islr_range", "pslr_azimuth", "islr_azimuth"):
+            assert abs(a[key] - b[key]) <= 0.1, key
+        assert abs(a["snr_db"] - b["snr_db"]) <= 0.05
+
+
+@pytest.mark.parametrize("nr, na", [(64, 64), (16384, 64), (64, 16384), (512, 2048)])
+def test_halfstore_extreme_shapes_lfm(nr, na):
+    cfg = config("c1", Nr=nr, Na=na, range_len=min(64, nr // 2), range_tbp=min(32, nr // 4),
+                 az_len=min(64, na // 2), az_tbp=min(32, na // 4), n_targets=1, spacing=4)
+    sc = simulate(cfg)
+    ref = O.rda(sc.raw, cfg)
+    img = run(cfg, sc.raw)
+    err = rel_l2(img, ref)
+    print(f"halfstore LFM {nr}x{na}: rel L2 {err:.3e}")
+    assert err <= TOL_HALF
+    t = sc.targets[0]
+    assert Q.peak_cell(img, t["m"], t["n"]) == (t["m"], t["n"])
+
+
+@pytest.mark.parametrize("nr, na", [(64, 64), (256, 512), (2048, 256), (1024, 8192)])
+def test_halfstore_hyperbolic_shapes(nr, na):
+    lr = min(512, nr // 2)
+    cfg = config("c2", Nr=nr, Na=na, range_len=lr, range_tbp=min(200.0, lr / 2.0),
+                 n_targets=1, spacing=8, exposure=min(1024, na // 2))
+    sc = simulate(cfg)
+    ref = O.rda(sc.raw, cfg)
+    img = run(cfg, sc.raw)
+    err = rel_l2(img, ref)
+    print(f"halfstore hyperbolic {nr}x{na}: rel L2 {err:.3e}")
+    assert err <= TOL_HALF
+    # A 32-pulse aperture (64 x 64) does not focus onto the seeded cell even
+    # in the oracle; the image's peak must be the oracle's.
+    t = sc.targets[0]
+    assert Q.peak_cell(img, t["m"], t["n"]) == Q.peak_cell(ref, t["m"], t["n"])
+
+
+def test_halfstore_power_of_two_scaling_is_exact():
+    """Scaling the raw data by 2^k scales every intermediate line by exactly
+    2^k in FP32; the per-line exponent absorbs it, so the image scales
+    bit-exactly even where plain FP16 would overflow (2^40) or flush to zero
+    (2^-40)."""
+    cfg, sc, _ = scene_and_oracle("c2", n_targets=2, Nr=1024, Na=1024, exposure=512)
+    base = run(cfg, sc.raw)
+    for k in (40, -40):
+        img = run(cfg, (sc.raw * np.float32(2.0 ** k)).astype(np.complex64))
+        assert np.array_equal(img, (base * np.float32(2.0 ** k)).astype(np.complex64)), k
+
+
+def test_halfstore_zero_scene_gives_zero_image():
+    cfg = config("c2", Nr=512, Na=1024, range_len=256, range_tbp=100.0, exposure=512)
+    img = run(cfg, np.zeros((cfg["Na"], cfg["Nr"]), np.complex64))
+    assert np.isfinite(img).all()
+    assert np.abs(img).max() == 0.0
+
+
+def test_halfstore_repeat_runs_bit_identical():
+    cfg, sc, _ = scene_and_oracle("c1")
+    with sar.Plan(cfg, precision=PREC) as p:
+        raw = dev(sc.raw)
+        a = host(p.execute(raw))
+        for _ in range(3):
+            b = host(p.execute(raw))
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_halfstore_step_entry_points_are_fp32(name):
+    """The step-by-step entry points exchange complex64 buffers, so a
+    half-storage plan runs them in FP32, bit-identical to an FP32 plan."""
+    cfg, sc, _ = scene_and_oracle(name)
+    outs = []
+    for prec in ("fp32", PREC):
+        with sar.Plan(cfg, precision=prec) as p:
+            raw = dev(sc.raw)
+            rc = empty((cfg["Na"], cfg["Nr"]))
+            tr = empty((cfg["Nr"], cfg["Na"]))
+            img = empty((cfg["Nr"], cfg["Na"]))
+            work = empty((cfg["Nr"], cfg["Na"]))
+            sar.sar_range_compress(p.handle, raw, rc)
+            sar.sar_corner_turn(p.handle, rc, tr, cfg["Na"], cfg["Nr"])
+            sar.sar_azimuth_compress(p.handle, tr, img, work)
+            outs.append(host(img))
+    assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32))
+
+
+def test_halfstore_workspace_layout():
+    """Two FP16 scene buffers (4 bytes per pixel each) and the per-line
+    exponents of both line directions, each 256-byte aligned."""
+    al = lambda x: (x + 255) // 256 * 256   # noqa: E731
+    for nr, na in [(256, 256), (4096, 4096), (64, 16384), (16384, 64)]:
+        cfg = config("c1", Nr=nr, Na=na, range_len=min(64, nr // 2), range_tbp=min(32, nr // 4),
+                     az_len=min(64, na // 2), az_tbp=min(32, na // 4))
+        with sar.Plan(cfg, precision=PREC) as p:
+            assert p.workspace_bytes == 2 * al(4 * nr * na) + al(4 * na) + al(4 * nr)
+
+
+def test_halfstore_rejects_overlapping_workspace():
+    torch = torch_cuda()
+    cfg, sc, _ = scene_and_oracle("c1")
+    with sar.Plan(cfg, precision=PREC) as p:
+        raw = dev(sc.raw)
+        pool = torch.empty(2 * sc.raw.size + p.workspace_bytes // 8 + 1, dtype=torch.complex64,
+                           device="cuda")
+        img = pool[:sc.raw.size].view(cfg["Nr"], cfg["Na"])
+        work = pool[sc.raw.size - 8:]      # 64 bytes inside the image
+        with pytest.raises(sar.SarError) as ei:
+            sar.sar_rda_execute(p.handle, raw, img, work, None)
+        assert ei.value.status == sar._lib.SAR_ERR_ALIAS
+
+
+def test_halfstore_scene_in_a_batch():
+    """A half-storage scene inside a batch runs through its own plan and
+    comes out bit-identical to a single-scene run."""
+    torch = torch_cuda()
+    cfgs = [config("c1"), config("c2", Nr=512, Na=1024, range_len=256, range_tbp=100.0,
+                                 n_targets=1, exposure=512), config("c1", seed=3)]
+    opts = [dict(precision=PREC), dict(precision=PREC), dict()]
+    scenes = [simulate(c) for c in cfgs]
+    params = [sar.make_params(c, **o) for c, o in zip(cfgs, opts)]
+    b = sar.sar_batch_plan(params, None)
+    try:
+        raws = [dev(s.raw) for s in scenes]
+        imgs = [empty(s.raw.shape[::-1]) for s in scenes]
+        work = torch.empty(sar.sar_batch_workspace_bytes(b) // 8 + 1, dtype=torch.complex64,
+                           device="cuda")
+        sar.sar_batch_execute(b, raws, imgs, work, None)
+        got = [host(im) for im in imgs]
+    finally:
+        torch.cuda.synchronize()
+        sar.sar_batch_destroy(b)
+    for c, o, s, g in zip(cfgs, opts, scenes, got):
+        with sar.Plan(c, **o) as p:
+            want = host(p.execute(dev(s.raw)))
+        assert np.array_equal(g.view(np.uint32), want.view(np.uint32))

@@ -74,7 +74,8 @@ def make(budget, slots=4, **kw):
 
 
 def test_footprint():
-    assert footprint_bytes(cfg(1024, 2048)) == 3 * 8 * 1024 * 2048
+    px = 1024 * 2048
+    assert footprint_bytes(cfg(1024, 2048)) == 24 * px + 4 * (1024 + 2048) + 1024
 
 
 def test_arena_against_brute_force():
