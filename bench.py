@@ -269,6 +269,9 @@ def batch_leg(torch, sar, dev):
     work = torch.empty(sar.sar_batch_workspace_bytes(b) // 8 + 1, dtype=torch.complex64,
                        device=dev)
     ms_batch, _ = timed(lambda: sar.sar_batch_execute(b, raws, imgs, work, s), 5, 2)
+    # the same batched launches issued directly on the null stream (no graph)
+    s0 = torch.cuda.default_stream()
+    ms_direct, _ = Timer(torch, s0)(lambda: sar.sar_batch_execute(b, raws, imgs, work, 0), 5, 2)
     # the same scenes one after another, one plan each, same stream
     plans = [sar.Plan(c, stream=s) for c in cfgs]
     torch.cuda.synchronize()
@@ -290,6 +293,7 @@ def batch_leg(torch, sar, dev):
             "sequential_ms": round(ms_seq, 3),
             "sequential_value": round(px / (ms_seq * 1e-3) / 1e6, 1),
             "speedup_vs_sequential": round(ms_seq / ms_batch, 3),
+            "direct_ms": round(ms_direct, 3),
             "hbm_frac_design": round(48 * px / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "autotuned_variants": tuned,
             "workload": "64 LFM scenes, Nr 1024..16384 x Na 512..8192 (seed 4), 3-9 targets, "
