@@ -202,8 +202,10 @@ sar_status sar_plan_get_table(sar_plan_t plan, int32_t which, void* host_dst,
  * azimuth and the fused schedule share launches: one line launch per (pass,
  * line length, precision) and one corner-turn launch per turn, each a grid
  * over all scenes' line groups or tiles (task lists in device memory).  Every
- * other scene (hyperbolic, unfused) runs as sar_rda_execute in the same
- * stream.  Each scene's image is bit-identical to its own sar_rda_execute.
+ * other scene (hyperbolic, unfused, half storage, and any scene of 2^22
+ * pixels or more, which fills the GPU with its own launches) runs as
+ * sar_rda_execute in the same stream, in scene order, after the shared
+ * launches.  Each scene's image is bit-identical to its own sar_rda_execute.
  */
 
 /* Plan `n` scenes (params ps[0..n-1], n >= 1): validates every parameter set

@@ -10,8 +10,9 @@
 // buffer pointers rebuilds the tasks and the graph.
 //
 // Scenes whose processing the batched launches do not cover (hyperbolic
-// azimuth, the unfused schedule, half storage) run through sar_rda_execute
-// inside the same stream (and graph).
+// azimuth, the unfused schedule, half storage) and scenes large enough to
+// fill the chip alone (see kShareBelowPx) run through sar_rda_execute inside
+// the same stream (and graph).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -81,9 +82,18 @@ void drop_graph(sar_batch_s* B)
     B->graph = nullptr;
 }
 
+// A scene of 4 Mpx or more fills the chip with its own launches (at least
+// 1024 line groups per pass), and run pass after pass it re-reads the
+// previous pass's output from the 256 MiB MALL when it is no larger than
+// that; sharing launches with other scenes would only separate its passes.
+// Such scenes run as sar_rda_execute, in scene order, inside the same
+// stream (and graph); the smaller ones share launches.
+constexpr long long kShareBelowPx = 1LL << 22;
+
 bool batched(const sar_params& p)
 {
-    return p.az_model == SAR_AZ_LFM && p.schedule == SAR_FUSED && p.precision != SAR_FP32_HALF_STORAGE;
+    return p.az_model == SAR_AZ_LFM && p.schedule == SAR_FUSED && p.precision != SAR_FP32_HALF_STORAGE &&
+           (long long)p.Na * p.Nr < kShareBelowPx;
 }
 
 // Build task arrays for this buffer set and upload them (synchronous).

@@ -14,7 +14,7 @@ import paper_2604_03585_amd as sar
 from gpu_util import dev, host, rel_l2, torch_cuda
 from oracle import oracle as O
 from oracle import quality as Q
-from sarsim import batch_configs, config, simulate
+from sarsim import batch_configs, config, lfm_scene, simulate
 
 pytestmark = pytest.mark.gpu
 
@@ -72,6 +72,26 @@ def test_batch_matches_single_scene_runs(graph):
         for i, (c, o, s) in enumerate(zip(cfgs, opts, scenes)):
             ref = single(c, o, s.raw)
             assert np.array_equal(rep[i].view(np.uint32), ref.view(np.uint32)), (i, c["name"], o)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_long_lines_and_large_scenes(graph):
+    """Lines of 8192 and 16384 points in shared launches (scenes below 2^22
+    pixels) next to a scene of 2^22 pixels, which runs its own launches after
+    them; every image bit-identical to its single-scene run."""
+    torch = torch_cuda()
+    cfgs = [lfm_scene(16384, 128, 1, 11, "r16k"), lfm_scene(128, 16384, 1, 12, "a16k"),
+            lfm_scene(8192, 256, 1, 13, "r8k"), lfm_scene(2048, 2048, 2, 14, "big"),
+            lfm_scene(256, 8192, 1, 15, "a8k")]
+    opts = [dict() for _ in cfgs]
+    scenes = [simulate(c) for c in cfgs]
+    stream = torch.cuda.Stream() if graph else 0
+    with torch.cuda.stream(stream) if graph else torch.cuda.stream(torch.cuda.current_stream()):
+        outs = run_batch(cfgs, opts, scenes, stream, reps=2)
+    for rep in outs:
+        for i, (c, o, s) in enumerate(zip(cfgs, opts, scenes)):
+            ref = single(c, o, s.raw)
+            assert np.array_equal(rep[i].view(np.uint32), ref.view(np.uint32)), (i, c["name"])
 
 
 def test_batch_against_oracle():
