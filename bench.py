@@ -16,6 +16,8 @@ Besides the headline it measures, each on the same GPU:
   kernels_ms    each kernel of the fused pipeline, timed inside the pipeline
                 with HIP events between the launches of a step on the stream
                 they run on (the slowest kernel carries the roofline figure);
+  hbm_copy_gbs  a plain device copy of one 128 MiB scene buffer (read + write
+                bytes per second): the achievable rate for a pass;
   unfused       the 3-dispatch comparator;
   split         the same scene with radix-16 butterflies on MFMA (split
                 FP16 / BF16 operands, FP32 accumulation), and with FP32
@@ -197,6 +199,11 @@ def headline(args, torch, sar, cfg, raw, dev):
     kern = {n: sum(ev[r][i].elapsed_time(ev[r][i + 1]) for r in range(reps)) / reps
             for i, n in enumerate(names)}
 
+    # ---- achievable HBM rate: a plain device copy of one scene buffer
+    # (the runtime's copy kernel), same size and stream as one pass ----
+    ms_copy, _ = timed(lambda: work.copy_(raw), 50, 5)
+    copy_gbs = 2.0 * raw.numel() * raw.element_size() / (ms_copy * 1e-3) / 1e9
+
     # ---- unfused 3-dispatch comparator ----
     uplan = sar.Plan(cfg, schedule="unfused")
     ms_unfused, _ = timed(lambda: sar.sar_rda_execute(uplan.handle, raw, img, work, stream),
@@ -225,7 +232,7 @@ def headline(args, torch, sar, cfg, raw, dev):
     torch.cuda.synchronize()
     plan.close()
     uplan.close()
-    return ms_event, ms_wall, ms_cold, kern, ms_unfused, split, images
+    return ms_event, ms_wall, ms_cold, kern, copy_gbs, ms_unfused, split, images
 
 
 def fft_leg(torch, sar, dev):
@@ -426,9 +433,9 @@ def main():
     px = Na * Nr
     raw = torch.from_numpy(sc.raw).to(dev)
 
-    ms_event, ms_wall, ms_cold, kern, ms_unfused, split, images = headline(args, torch, sar, cfg,
-                                                                          raw, dev)
-    log(f"headline: {ms_wall:.4f} ms/step, kernels {kern}")
+    ms_event, ms_wall, ms_cold, kern, copy_gbs, ms_unfused, split, images = headline(
+        args, torch, sar, cfg, raw, dev)
+    log(f"headline: {ms_wall:.4f} ms/step, kernels {kern}, copy {copy_gbs:.0f} GB/s")
     ms_per_step = ms_wall
     value = px / (ms_per_step * 1e-3) / 1e6
     dom = max(kern, key=kern.get)
@@ -466,6 +473,7 @@ def main():
         "hbm_frac_design": round(design_fused / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "fft_gflops": round(flops / (ms_per_step * 1e-3) / 1e9, 1),
         "kernels_ms": {k: round(v, 4) for k, v in kern.items()},
+        "hbm_copy_gbs": round(copy_gbs, 1),
         "unfused": {"ms_per_step": round(ms_unfused, 4),
                     "value": round(px / (ms_unfused * 1e-3) / 1e6, 1),
                     "design_bytes_per_px": 128,

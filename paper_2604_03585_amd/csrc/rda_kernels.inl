@@ -413,10 +413,17 @@ __global__ __launch_bounds__(256) void k_corner_turn_batch(const TurnTask* __res
 //     tab[b * 24 + t * 3 + j] = coefficient of u^j, tap t.
 // The interpolation error is 2.2e-8 in FP64 (below the FP32 rounding of the
 // coefficients; tested against the oracle's weights); the kernels copy the
-// 12 KiB table into LDS.
+// 12 KiB table into LDS (14 KiB there, see RCMC_LDS_STRIDE).
 constexpr int RCMC_INTERVALS = 128;
 constexpr int RCMC_PER_INTERVAL = 24;
 constexpr int RCMC_TAB = RCMC_INTERVALS * RCMC_PER_INTERVAL;
+// The LDS copy places the intervals 7 vectors (28 floats) apart: the lanes of
+// a wave read random intervals, and with an odd stride in 16-byte units the
+// same vector of different intervals falls into every bank group, where a
+// stride of 6 reaches only half of them (twice the bank conflicts).  The
+// seventh vector of each interval is padding and never read.
+constexpr int RCMC_LDS_STRIDE = 28;
+constexpr int RCMC_LDS_FLOATS = RCMC_INTERVALS * RCMC_LDS_STRIDE;
 
 #if SAR_PART == 0
 __device__ double i0_fp64(double y)
@@ -538,12 +545,15 @@ __global__ void k_gen_hyper_tables(double* __restrict__ stretch, double* __restr
 }
 #endif
 
+// Global table (24 floats per interval) -> LDS (RCMC_LDS_STRIDE floats per
+// interval); lds_tab holds RCMC_LDS_FLOATS floats.
 __device__ __forceinline__ void load_rcmc_table(float* __restrict__ lds_tab,
                                                 const float* __restrict__ tab, int tid, int nthreads)
 {
-    static_assert(RCMC_TAB % 4 == 0, "16-byte copies");
+    static_assert(RCMC_PER_INTERVAL == 24 && RCMC_LDS_STRIDE % 4 == 0, "16-byte copies");
+    constexpr int V = RCMC_PER_INTERVAL / 4, VS = RCMC_LDS_STRIDE / 4;
     for (int i = tid; i < RCMC_TAB / 4; i += nthreads)
-        ((float4*)lds_tab)[i] = ((const float4*)tab)[i];
+        ((float4*)lds_tab)[(i / V) * VS + i % V] = ((const float4*)tab)[i];
 }
 
 // sum_t w_t(x) a_t with the weights from the LDS table.
@@ -553,7 +563,7 @@ __device__ __forceinline__ float2 rcmc_combine(float x, const float* __restrict_
     const float xf = x * (float)RCMC_INTERVALS;
     const int b = min((int)xf, RCMC_INTERVALS - 1);
     const float u = xf - (float)b;
-    const float4* p = (const float4*)(tab + b * RCMC_PER_INTERVAL);
+    const float4* p = (const float4*)(tab + b * RCMC_LDS_STRIDE);
     float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {                 // taps 4h .. 4h+3: three vectors
@@ -723,6 +733,7 @@ k_rcmc_az(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
     // The weight table and the line buffers share LDS: the table is only read
     // while the RCMC samples are formed, before the first FFT exchange.
     float* tab = (float*)smem;
+    static_assert(L::LDS_BYTES >= RCMC_LDS_FLOATS * (int)sizeof(float), "table fits the line LDS");
     const int lines = ra.nr;
     const int groups = (lines + L::LPW - 1) / L::LPW;
     const int g = xcd_group(blockIdx.x, groups);
@@ -902,6 +913,7 @@ k_rcmc_az2(const void* __restrict__ A_, float2* __restrict__ out, RcmcArgs ra,
     constexpr int E = line_e(N);
     extern __shared__ __align__(16) float2 smem[];
     float* tab = (float*)smem;                    // shares LDS with the line buffers
+    static_assert(L::LDS_BYTES >= RCMC_LDS_FLOATS * (int)sizeof(float), "table fits the line LDS");
     const int pairs = ra.nr / 2;
     const int groups = (pairs + L::LPW - 1) / L::LPW;
     const int g = xcd_group(blockIdx.x, groups);
@@ -945,6 +957,8 @@ k_rcmc_az2w(const float2* __restrict__ A, float2* __restrict__ out, RcmcArgs ra,
     static_assert(S <= 1024, "two line slots per workgroup");
     extern __shared__ __align__(16) float2 smem[];
     float* tab = (float*)smem;
+    static_assert(2 * G::LDS * (int)sizeof(float2) >= RCMC_LDS_FLOATS * (int)sizeof(float),
+                  "table fits the two line buffers");
     const int pairs = ra.nr / 2;
     const int pr = xcd_group(blockIdx.x, pairs);
     const int n = 2 * pr;
@@ -983,7 +997,7 @@ template <int TAPS>
 __global__ __launch_bounds__(256) void k_rcmc_interp(const float2* __restrict__ A,
                                                      float2* __restrict__ out, int na, RcmcArgs ra)
 {
-    __shared__ __align__(16) float tab[RCMC_TAB];
+    __shared__ __align__(16) float tab[RCMC_LDS_FLOATS];
     if constexpr (TAPS != 0) {
         load_rcmc_table(tab, ra.table, threadIdx.x, 256);
         __syncthreads();
@@ -1212,7 +1226,7 @@ static hipError_t launch_line_n(LineOp op, const float2* in, float2* out, int li
     case LineOp::RcmcAz: {
         const int groups = (lines + L::LPW - 1) / L::LPW;
         if (groups == 0) return hipSuccess;
-        static_assert(L::LDS_BYTES >= RCMC_TAB * (int)sizeof(float), "table fits the line LDS");
+        static_assert(L::LDS_BYTES >= RCMC_LDS_FLOATS * (int)sizeof(float), "table fits the line LDS");
         // variant bit 1: one output row per line slot instead of two; bit 2
         // (FP32, N = 4096 or 8192): the two rows on two line slots' threads
         // (k_rcmc_az2w) instead of one's
