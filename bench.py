@@ -92,10 +92,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel: str, profiles_dir: str | None = None):
-    """HBM bytes per launch from the committed counter summary of ``kernel``
-    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's counts), if it was
-    taken on the current kernel sources; else None."""
+def _recorded(tag: str, kernel: str, profiles_dir: str | None):
     d = profiles_dir or os.path.join(ROOT, "profiles")
     want = kernel_source_hash()
     if not os.path.isdir(d):
@@ -104,12 +101,31 @@ def recorded_traffic(kernel: str, profiles_dir: str | None = None):
         if not name.endswith((".md", ".txt")):
             continue
         for line in open(os.path.join(d, name)):
-            if not line.startswith("traffic-record:"):
+            if not line.startswith(tag + ":"):
                 continue
             rec = json.loads(line.split(":", 1)[1])
             if rec.get("bench_kernel") == kernel and rec.get("source_sha256") == want:
                 return rec
     return None
+
+
+def recorded_traffic(kernel: str, profiles_dir: str | None = None):
+    """HBM bytes per launch from the committed counter summary of ``kernel``
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's counts), if it was
+    taken on the current kernel sources; else None."""
+    return _recorded("traffic-record", kernel, profiles_dir)
+
+
+def recorded_issue(kernel: str, profiles_dir: str | None = None):
+    """VALU / LDS wave-instruction counts per launch of ``kernel`` from the
+    committed SQ counter summary, if taken on the current kernel sources."""
+    return _recorded("issue-record", kernel, profiles_dir)
+
+
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64 VALU
+# instruction occupies its SIMD for 4 cycles without packed FP32, an FP32
+# transcendental for 16).
+VALU_LANE_INSTR_PEAK = 256 * 4 * 16 * 2.4e9
 
 
 class Timer:
@@ -442,6 +458,19 @@ def main():
     dom_bytes = KERNEL_BYTES_PER_PX[dom] * px
     achieved = dom_bytes / (kern[dom] * 1e-3) / 1e9
     trec = recorded_traffic(dom)
+    irec = recorded_issue(dom)
+    valu_issue = None
+    if irec:
+        t = kern[dom] * 1e-3
+        cycles = 4 * irec["valu_wave_instr"] + 12 * irec["trans_wave_instr"]
+        valu_issue = {"bound": "valu_issue", "kernel": dom,
+                      "achieved": round(irec["valu_wave_instr"] * 64 / t / 1e12, 2),
+                      "peak": round(VALU_LANE_INSTR_PEAK / 1e12, 2),
+                      "unit": "T lane-instr/s",
+                      "frac": round(cycles * 16 / t / VALU_LANE_INSTR_PEAK, 4),
+                      "valu_per_px": round(irec["valu_wave_instr"] * 64 / px, 1),
+                      "lds_conflict_ratio": irec["lds_conflict_ratio"],
+                      "source": irec["source"]}
 
     design_fused = 64 * px        # range 16 + turn 16 + az FFT 16 + RCMC/az 16
     design_unfused = 128 * px     # range 48 + turn 16 + az FFT 16 + RCMC 16 + xH 16 + IFFT 16
@@ -488,6 +517,8 @@ def main():
                      "algorithmic_bytes": dom_bytes,
                      "kernel_us": round(kern[dom] * 1e3, 2)},
     }
+    if valu_issue:
+        out["valu_issue"] = valu_issue
     if split:
         out["split"] = split
 
