@@ -54,7 +54,7 @@ typedef enum {
     SAR_ERR_ALIAS = 4,       /* buffers overlap where they must not          */
     SAR_ERR_NO_MEMORY = 5,   /* a device or host allocation failed           */
     SAR_ERR_HIP = 6,         /* a HIP runtime call or launch failed          */
-    SAR_ERR_UNSUPPORTED = 7  /* valid request this build does not implement  */
+    SAR_ERR_UNSUPPORTED = 7  /* valid request the library does not implement */
 } sar_status;
 
 typedef enum { SAR_AZ_LFM = 0, SAR_AZ_HYPERBOLIC = 1 } sar_az_model;
