@@ -76,7 +76,7 @@ def test_halfstore_extreme_shapes_lfm(nr, na):
     assert Q.peak_cell(img, t["m"], t["n"]) == (t["m"], t["n"])
 
 
-@pytest.mark.parametrize("nr, na", [(64, 64), (256, 512), (2048, 256), (1024, 8192)])
+@pytest.mark.parametrize("nr, na", [(64, 64), (256, 512), (2048, 256), (1024, 8192), (64, 16384)])
 def test_halfstore_hyperbolic_shapes(nr, na):
     lr = min(512, nr // 2)
     cfg = config("c2", Nr=nr, Na=na, range_len=lr, range_tbp=min(200.0, lr / 2.0),

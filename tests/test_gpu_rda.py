@@ -97,6 +97,25 @@ def test_extreme_shapes(nr, na):
     assert Q.peak_cell(img, t["m"], t["n"]) == (t["m"], t["n"])
 
 
+@pytest.mark.parametrize("nr, na", [(16384, 64), (64, 16384), (256, 8192)])
+@pytest.mark.parametrize("schedule", ["fused", "unfused"])
+def test_extreme_shapes_hyperbolic(nr, na, schedule):
+    """Longest azimuth lines through RCMC (16384 points: the two-row kernel at
+    its largest line, 1024 threads per line) and longest range lines, in the
+    hyperbolic geometry."""
+    lr = min(512, nr // 2)
+    cfg = config("c2", Nr=nr, Na=na, range_len=lr, range_tbp=min(200.0, lr / 2.0),
+                 n_targets=1, spacing=8, exposure=min(1024, na // 2))
+    sc = simulate(cfg)
+    ref = O.rda(sc.raw, cfg)
+    img = run_gpu(cfg, sc.raw, schedule)
+    err = rel_l2(img, ref)
+    print(f"hyperbolic {nr}x{na} {schedule}: rel L2 {err:.3e}")
+    assert err <= TOL_RDA
+    t = sc.targets[0]
+    assert Q.peak_cell(img, t["m"], t["n"]) == Q.peak_cell(ref, t["m"], t["n"])
+
+
 def test_noise_only_scene():
     """A scene with no targets (the image is compressed noise only)."""
     cfg, sc, ref = scene_and_oracle("c1", n_targets=0)
