@@ -22,8 +22,9 @@ Besides the headline it measures, each on the same GPU:
   split         the same scene with radix-16 butterflies on MFMA (split
                 FP16 / BF16 operands, FP32 accumulation), and with FP32
                 arithmetic over FP16 intermediate buffers (fp32_halfstore);
-  fft_batched   batched 4096-point line FFTs alone (batch 256 and 4096), FP32
-                and split precisions, in GFLOPS;
+  fft_batched   batched 4096-point line FFTs alone (batch 256 and 4096): FP32,
+                FP32 in the split real/imaginary LDS layout, and the split
+                precisions, in GFLOPS (the paper's Table I comparison);
   batch         64 scenes of uneven size (LFM, Nr 1024..16384, Na 512..8192)
                 in shared launches replayed from a hipGraph, autotuned, vs the
                 same scenes run one after another;
@@ -253,24 +254,41 @@ def headline(args, torch, sar, cfg, raw, dev):
 
 def fft_leg(torch, sar, dev):
     """Batched line FFTs alone (the paper's Table I setting: N = 4096, batch
-    256; also batch 4096): GFLOPS at 5 N log2 N per transform, FP32 radix-16
-    Stockham vs the split FP16 / BF16 MFMA butterflies."""
+    256; also batch 4096): GFLOPS at 5 N log2 N per transform for the three
+    kernels of that table's comparison: FP32 radix-16 Stockham exchanging
+    complex pairs through LDS, the same FP32 butterflies with the split
+    real/imaginary LDS layout (forward variant 2), and the split FP16 / BF16
+    MFMA butterflies (which need that layout)."""
+    import tempfile
     from sarsim import lfm_scene
     s = torch.cuda.current_stream()
+    arch = torch.cuda.get_device_properties(dev).gcnArchName.split(":")[0]
     out = {"n": 4096, "flops_per_fft": 5 * 4096 * 12}
-    for batch in (256, 4096):
-        cfg = lfm_scene(4096, batch, 1, 1, "fft")
-        a = torch.randn(batch * 4096, dtype=torch.complex64, device=dev)
-        b = torch.empty_like(a)
-        for prec in ("fp32", "split_fp16", "split_bf16"):
-            with sar.Plan(cfg, precision=prec) as p:
-                ms, _ = Timer(torch, s, 30.0)(lambda: sar.sar_fft_lines(p.handle, 0, 0, a, b, batch, s),
-                                        200 if batch == 256 else 50, 5)
-            out[f"batch{batch}_{prec}"] = {
-                "us": round(ms * 1e3, 2),
-                "gflops": round(5 * 4096 * 12 * batch / (ms * 1e-3) / 1e9, 1),
-                "hbm_frac": round(16 * 4096 * batch / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
-    out["paper_context"] = "Apple M1 radix-8 Stockham 138 GFLOPS, MMA CT DIF 128 GFLOPS (Table I)"
+    legs = [("fp32", "fp32", 0), ("fp32_split_layout", "fp32", 2),
+            ("split_fp16", "split_fp16", 0), ("split_bf16", "split_bf16", 0)]
+    with tempfile.TemporaryDirectory() as td:
+        for batch in (256, 4096):
+            cfg = lfm_scene(4096, batch, 1, 1, "fft")
+            a = torch.randn(batch * 4096, dtype=torch.complex64, device=dev)
+            b = torch.empty_like(a)
+            for name, prec, variant in legs:
+                # the plan copies the forward kernel's variant from the tuning table
+                path = os.path.join(td, f"{name}.jsonl")
+                with open(path, "w") as f:
+                    f.write(json.dumps({"arch": arch, "kind": "fwd", "n": 4096, "prec": 0,
+                                        "variant": variant}) + "\n")
+                sar.sar_tune_load(path)
+                with sar.Plan(cfg, precision=prec) as p:
+                    ms, _ = Timer(torch, s, 30.0)(
+                        lambda: sar.sar_fft_lines(p.handle, 0, 0, a, b, batch, s),
+                        200 if batch == 256 else 50, 5)
+                out[f"batch{batch}_{name}"] = {
+                    "us": round(ms * 1e3, 2),
+                    "gflops": round(5 * 4096 * 12 * batch / (ms * 1e-3) / 1e9, 1),
+                    "hbm_frac": round(16 * 4096 * batch / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
+    sar.sar_tune_load(None)
+    out["paper_context"] = ("Apple M1: radix-8 Stockham 138 GFLOPS, CT MMA 128, CT scalar in the "
+                            "split layout 120 (Table I)")
     return out
 
 

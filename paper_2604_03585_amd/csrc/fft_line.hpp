@@ -238,7 +238,11 @@ __device__ __forceinline__ void load_tw(PassTw<N, P>& pt, const float2* __restri
 
 // One Stockham pass P of an N-point line (see the header comment), with its
 // twiddles already loaded.
-template <int N, int P, bool INV>
+// SPLIT: the exchange keeps real and imaginary parts in two float arrays of
+// the line's LDS (re[0, LDS), im[LDS, 2 LDS)), two 4-byte accesses per point
+// instead of one 8-byte access: the layout the MFMA passes need, here with
+// FP32 butterflies, so that the two can be compared at equal layout.
+template <int N, int P, bool INV, bool SPLIT = false>
 __device__ __forceinline__ void fft_pass(float2 (&x)[line_e(N)], float2* __restrict__ lds,
                                          const PassTw<N, P>& pt, int t)
 {
@@ -269,14 +273,32 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[line_e(N)], float2* __restr
             for (int i = 0; i < R; ++i) x[q + i * B] = v[i];
         } else {
             const int base = (j / NS) * NS * R + jm;
+            if constexpr (SPLIT) {
+                float* re = (float*)lds;
+                float* im = re + G::LDS;
 #pragma unroll
-            for (int i = 0; i < R; ++i) lds[lds_pad(base + i * NS)] = v[i];
+                for (int i = 0; i < R; ++i) {
+                    re[lds_pad(base + i * NS)] = v[i].x;
+                    im[lds_pad(base + i * NS)] = v[i].y;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < R; ++i) lds[lds_pad(base + i * NS)] = v[i];
+            }
         }
     }
     if constexpr (!LAST) {
         __syncthreads();
+        if constexpr (SPLIT) {
+            const float* re = (const float*)lds;
+            const float* im = re + G::LDS;
 #pragma unroll
-        for (int m = 0; m < E; ++m) x[m] = lds[lds_pad(t + m * G::T)];
+            for (int m = 0; m < E; ++m)
+                x[m] = make_float2(re[lds_pad(t + m * G::T)], im[lds_pad(t + m * G::T)]);
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; ++m) x[m] = lds[lds_pad(t + m * G::T)];
+        }
         __syncthreads();
     }
 }
@@ -288,7 +310,7 @@ struct NoOp {
     __device__ __forceinline__ void operator()() const {}
 };
 
-template <int N, bool INV, bool TWP, int P, class F>
+template <int N, bool INV, bool TWP, int P, bool SPLIT, class F>
 __device__ __forceinline__ void fft_from(float2 (&x)[line_e(N)], float2* __restrict__ lds,
                                          const float2* __restrict__ tw, int t, F&& before_last)
 {
@@ -296,17 +318,18 @@ __device__ __forceinline__ void fft_from(float2 (&x)[line_e(N)], float2* __restr
         if constexpr (P == LineGeom<N>::NP - 1) before_last();
         PassTw<N, P> cur;
         load_tw<N, P, TWP>(cur, tw, t);
-        fft_pass<N, P, INV>(x, lds, cur, t);
-        fft_from<N, INV, TWP, P + 1>(x, lds, tw, t, before_last);
+        fft_pass<N, P, INV, SPLIT>(x, lds, cur, t);
+        fft_from<N, INV, TWP, P + 1, SPLIT>(x, lds, tw, t, before_last);
     }
 }
 
-// TWP selects twiddles by products (fewer loads, more VALU) or table reads.
-template <int N, bool INV, bool TWP = true, class F = NoOp>
+// TWP selects twiddles by products (fewer loads, more VALU) or table reads;
+// SPLIT the split real/imaginary exchange layout (see fft_pass).
+template <int N, bool INV, bool TWP = true, bool SPLIT = false, class F = NoOp>
 __device__ __forceinline__ void fft_line(float2 (&x)[line_e(N)], float2* __restrict__ lds,
                                          const float2* __restrict__ tw, int t, F&& before_last = F())
 {
-    fft_from<N, INV, TWP, 0>(x, lds, tw, t, before_last);
+    fft_from<N, INV, TWP, 0, SPLIT>(x, lds, tw, t, before_last);
 }
 
 }  // namespace sar

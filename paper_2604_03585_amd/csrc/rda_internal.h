@@ -56,7 +56,8 @@ struct RcmcHost {
 //  Forward: out = FFT(in) * scale;  Inverse: out = unscaled IFFT(in) * scale
 //  RcmcAz:  out[n] = IFFT(RCMC(in)[n] * phase / n), rh required, lines = rh->nr
 //  prec: 0 FP32 butterflies, 1 split FP16 / 2 split BF16 radix-16 butterflies on MFMA
-//  variant (autotuned): bit 0 twiddles from the table instead of by products,
+//  variant (autotuned): bit 0 twiddles from the table instead of by products
+//  (Forward / Inverse FP32 also bit 1: split real/imaginary LDS exchange),
 //  bit 1 one RCMC output row per line slot instead of two, bit 2 the two RCMC
 //  rows on two line slots' threads instead of one's (FP32, N = 4096 / 8192)
 hipError_t launch_line(LineOp op, int n, const void* in, void* out, int lines, const void* H,

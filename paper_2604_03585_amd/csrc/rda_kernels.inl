@@ -126,13 +126,13 @@ template <int N, int PREC> constexpr int line_wpe() { return (N == 4096 && PREC 
 
 // Line transform in the requested butterfly precision: FP32 VALU passes, or
 // split FP16 / BF16 radix-16 passes on MFMA (twiddles and filters in FP32).
-template <int N, bool INV, int PREC, bool TWP = true, class F = NoOp>
+template <int N, bool INV, int PREC, bool TWP = true, bool SPLIT = false, class F = NoOp>
 __device__ __forceinline__ void fft_any(float2 (&x)[line_e(N)], float2* __restrict__ lds,
                                         const float2* __restrict__ tw, int sub, int t,
                                         F&& before_last = F())
 {
     if constexpr (PREC == PREC_FP32) {
-        fft_line<N, INV, TWP>(x, lds, tw, t, before_last);
+        fft_line<N, INV, TWP, SPLIT>(x, lds, tw, t, before_last);
     } else {
         using L = LineLaunch<N>;
         before_last();
@@ -172,8 +172,9 @@ enum LineKind { LK_FUSED = 0, LK_FWD = 1, LK_INV = 2 };
 //  LK_FWD:   out = FFT(in) * scale;  LK_INV: out = IFFT_unscaled(in) * scale
 // One group of LPW lines starting at line g * LPW of `in` / `out`.  TWP:
 // twiddles by products (true) or straight table reads (false), chosen per
-// line length by the autotuner.
-template <int N, int KIND, int PREC, bool TWP>
+// line length by the autotuner; SPLIT (FP32 forward / inverse): the split
+// real/imaginary exchange layout.
+template <int N, int KIND, int PREC, bool TWP, bool SPLIT = false>
 __device__ __forceinline__ void line_group(const float2* in, float2* out, int lines,
                                            const float2* __restrict__ H,
                                            const float2* __restrict__ tw, float scale, int g,
@@ -204,7 +205,7 @@ __device__ __forceinline__ void line_group(const float2* in, float2* out, int li
         if constexpr (L::RECOMPUTE_INV_TW) asm volatile("" : "+v"(ti));   // hide ti == t
         fft_any<N, true, PREC, TWP>(x, lds, tw, sub, ti);
     } else {
-        fft_any<N, KIND == LK_INV, PREC, TWP>(x, lds, tw, sub, t);
+        fft_any<N, KIND == LK_INV, PREC, TWP, SPLIT>(x, lds, tw, sub, t);
         if (scale != 1.0f) {
 #pragma unroll
             for (int m = 0; m < E; ++m) x[m] = c_scale(x[m], scale);
@@ -213,14 +214,15 @@ __device__ __forceinline__ void line_group(const float2* in, float2* out, int li
     if (live) store_line<N>(x, out + (size_t)line * N, t);
 }
 
-template <int N, int KIND, int PREC, bool TWP>
+template <int N, int KIND, int PREC, bool TWP, bool SPLIT = false>
 __global__ __launch_bounds__(LineLaunch<N>::BLOCK)
 __attribute__((amdgpu_waves_per_eu(line_wpe<N, PREC>()))) void
 k_line(const float2* in, float2* out, int lines, const float2* __restrict__ H,
        const float2* __restrict__ tw, float scale)
 {
+    static_assert(!SPLIT || (PREC == PREC_FP32 && KIND != LK_FUSED), "split layout: FP32 FFT only");
     extern __shared__ __align__(16) float2 smem[];
-    line_group<N, KIND, PREC, TWP>(in, out, lines, H, tw, scale, blockIdx.x, smem);
+    line_group<N, KIND, PREC, TWP, SPLIT>(in, out, lines, H, tw, scale, blockIdx.x, smem);
 }
 
 // Batched form: the line groups of many scenes (tasks) in one launch.  The
@@ -1188,6 +1190,17 @@ static hipError_t set_lds_limit()
             hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, L::LDS_BYTES);
         if (e != hipSuccess) return e;
     }
+    if constexpr (PREC == PREC_FP32) {
+        const void* split[] = {(const void*)k_line<N, LK_FWD, PREC, true, true>,
+                               (const void*)k_line<N, LK_FWD, PREC, false, true>,
+                               (const void*)k_line<N, LK_INV, PREC, true, true>,
+                               (const void*)k_line<N, LK_INV, PREC, false, true>};
+        for (const void* f : split) {
+            const hipError_t e =
+                hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, L::LDS_BYTES);
+            if (e != hipSuccess) return e;
+        }
+    }
     return hipSuccess;
 }
 
@@ -1198,7 +1211,19 @@ static hipError_t launch_k_line(const float2* in, float2* out, int lines, const 
     using L = LineLaunch<N>;
     const int groups = (lines + L::LPW - 1) / L::LPW;
     if (groups == 0) return hipSuccess;
-    // variant bit 0: twiddles from the table (FP32 butterflies only)
+    // variant bit 0: twiddles from the table (FP32 butterflies only); bit 1
+    // (FP32 forward / inverse): the split real/imaginary exchange layout
+    if constexpr (PREC == PREC_FP32 && KIND != LK_FUSED) {
+        if (variant & 2) {
+            if (variant & 1)
+                hipLaunchKernelGGL((k_line<N, KIND, PREC, false, true>), dim3(groups), dim3(L::BLOCK),
+                                   L::LDS_BYTES, s, in, out, lines, H, tw, scale);
+            else
+                hipLaunchKernelGGL((k_line<N, KIND, PREC, true, true>), dim3(groups), dim3(L::BLOCK),
+                                   L::LDS_BYTES, s, in, out, lines, H, tw, scale);
+            return hipGetLastError();
+        }
+    }
     if (PREC == PREC_FP32 && (variant & 1))
         hipLaunchKernelGGL((k_line<N, KIND, PREC, false>), dim3(groups), dim3(L::BLOCK),
                            L::LDS_BYTES, s, in, out, lines, H, tw, scale);

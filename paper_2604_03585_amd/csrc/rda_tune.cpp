@@ -54,9 +54,9 @@ std::once_flag g_env_once;
 bool valid_variant(int kind, int v)
 {
     switch (kind) {
-    case sar::TK_FUSED:
+    case sar::TK_FUSED: return v == 0 || v == 1;
     case sar::TK_FWD:
-    case sar::TK_INV: return v == 0 || v == 1;
+    case sar::TK_INV: return v >= 0 && v <= 3;
     case sar::TK_RCMC: return v >= 0 && v <= 7;
     case sar::TK_BATCH_FUSED: return v >= 0 && v <= 15 && (v & 2) == 0;
     default: return false;
@@ -362,6 +362,10 @@ sar_status sar_autotune(const sar_params* p, const char* cache_path)
             if (r.key.kind == kind && r.key.n == n) return SAR_OK;
         std::vector<Candidate> cs{{0, 0.f}};
         if (fp32) cs.push_back({1, 0.f});
+        if (fp32 && kind != sar::TK_FUSED) {          // split real/imaginary exchange layout
+            cs.push_back({2, 0.f});
+            cs.push_back({3, 0.f});
+        }
         const sar::LineOp op = kind == sar::TK_FUSED ? sar::LineOp::Fused
                                : kind == sar::TK_FWD ? sar::LineOp::Forward
                                                      : sar::LineOp::Inverse;

@@ -136,3 +136,34 @@ def test_batch_variants_bit_identical_to_single(tmp_path, variant):
             assert np.array_equal(host(img).T, single)
     finally:
         sar.sar_batch_destroy(b)
+
+
+def _lfm_plan_cfg(n):
+    return dict(Nr=n, Na=64, range_len=max(2, n // 4), range_tbp=max(1.0, n / 8.0),
+                az_model="lfm", az_len=32, az_tbp=8.0, lam=0.0, v=0.0, r_near=0.0,
+                rcmc_taps=0, rcmc_beta=2.5)
+
+
+@pytest.mark.parametrize("n", [64, 512, 4096, 16384])
+@pytest.mark.parametrize("inverse", [0, 1])
+def test_split_layout_line_fft_bit_identical(tmp_path, n, inverse):
+    """Forward / inverse variants 2 and 3 exchange real and imaginary parts
+    through two LDS float arrays; the butterflies are the same, so each is
+    bit-identical to variant 0 / 1, and within FP32 rounding of the oracle."""
+    from gpu_util import empty, rand_c64
+    rng = np.random.Generator(np.random.PCG64(900 + n + inverse))
+    lines = 2 * max(1, 256 // (n // 16)) + 3
+    x = rand_c64(rng, (lines, n))
+    kind = "inv" if inverse else "fwd"
+    outs = {}
+    for v in (0, 1, 2, 3):
+        write_cache(tmp_path / f"v{v}.jsonl", [(kind, n, 0, v)])
+        assert sar.sar_tune_variant(KINDS.index(kind), n, 0) == v
+        with sar.Plan(_lfm_plan_cfg(n)) as p:
+            out = empty((lines, n))
+            sar.sar_fft_lines(p.handle, 0, inverse, dev(x), out, lines)
+            outs[v] = host(out)
+    assert np.array_equal(outs[2].view(np.uint32), outs[0].view(np.uint32))
+    assert np.array_equal(outs[3].view(np.uint32), outs[1].view(np.uint32))
+    ref = np.stack([O.fft(r, inverse=bool(inverse)) for r in x])
+    assert rel_l2(outs[2], ref) < 2e-6

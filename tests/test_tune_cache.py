@@ -17,6 +17,8 @@ CACHE = """\
 {"arch":"gfx950","kind":"fused","n":3000,"prec":0,"variant":1}
 {"arch":"gfx950","kind":"fused","n":256,"prec":7,"variant":1}
 {"arch":"gfx950","kind":"nonsense","n":256,"prec":0,"variant":1}
+{"arch":"gfx950","kind":"inv","n":1024,"prec":0,"variant":3}
+{"arch":"gfx950","kind":"fwd","n":1024,"prec":0,"variant":4}
 not json at all
 {"arch":"gfx950","kind":"fwd","n":256,"prec":0}
 """
@@ -46,11 +48,13 @@ def test_cache_entries_for_this_arch(cache):
 def test_invalid_lines_are_ignored(cache):
     sar.sar_tune_load(cache, "gfx950")
     v = sar.sar_tune_variant
-    assert v(_lib.TUNE_FUSED, 2048, 0) == 0          # variant 2 is not a line-kernel variant
+    assert v(_lib.TUNE_FUSED, 2048, 0) == 0          # variant 2 is not a fused-kernel variant
     assert v(_lib.TUNE_BATCH_FUSED, 2048, 0) == 0    # bit 1 is not a batch variant
     assert v(_lib.TUNE_FUSED, 3000, 0) == 0          # not a power of two
     assert v(_lib.TUNE_FUSED, 256, 7) == 0           # unknown precision
     assert v(_lib.TUNE_FWD, 256, 0) == 0             # no variant field
+    assert v(_lib.TUNE_INV, 1024, 0) == 3            # split layout + table twiddles
+    assert v(_lib.TUNE_FWD, 1024, 0) == 0            # bit 2 is not a line-kernel variant
 
 
 def test_other_arch_and_clear(cache):
