@@ -495,7 +495,7 @@ def main():
     flops = 2 * Na * 5 * Nr * math.log2(Nr) + 2 * Nr * 5 * Na * math.log2(Na)
 
     out = {
-        "metric": "RDA Mpixel/s at 4096^2 FP32 (fused), % HBM peak; p99 scene latency",
+        "metric": "RDA Mpixel/s at 4096^2 FP32 (fused vs unfused, % HBM peak); p99 scene latency",
         "value": round(value, 1),
         "unit": "Mpixel/s",
         "n_gpus": 1,

@@ -39,3 +39,18 @@ def test_kernel_source_hash_covers_the_kernel_files():
     for f in bench.KERNEL_SOURCES:
         assert os.path.exists(os.path.join(ROOT, "paper_2604_03585_amd", "csrc", f)), f
     assert len(bench.kernel_source_hash()) == 16
+
+
+def test_issue_record_matches_only_current_sources(tmp_path):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    good = {"bench_kernel": "rcmc_azimuth", "source_sha256": bench.kernel_source_hash(),
+            "valu_wave_instr": 1000, "trans_wave_instr": 10, "lds_wave_instr": 5,
+            "lds_conflict_ratio": 1.5, "source": "x"}
+    stale = dict(good, source_sha256="f" * 16)
+    (prof / "a.md").write_text("issue-record: " + json.dumps(stale) + "\n"
+                               "traffic-record: " + json.dumps(good) + "\n")
+    d = str(prof)
+    assert bench.recorded_issue("rcmc_azimuth", d) is None          # stale, other tag
+    (prof / "b.md").write_text("issue-record: " + json.dumps(good) + "\n")
+    assert bench.recorded_issue("rcmc_azimuth", d)["valu_wave_instr"] == 1000
