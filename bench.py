@@ -30,7 +30,8 @@ Besides the headline it measures, each on the same GPU:
                 same scenes run one after another;
   serve         Poisson arrivals of scenes 1024^2 .. 8192 x 16384 from a pool
                 of 32 device-resident scenes at 0.7 x the measured capacity,
-                admitted under an HBM budget: throughput, p50 / p99 latency;
+                admitted under an HBM budget: throughput, p50 / p99 latency
+                (FP32, split FP16 and half storage at 64 GiB, FP32 at 16 GiB);
   cpu_baseline  the FP64 CPU oracle on the host cores, on the headline scene;
                 its image also gives the accuracy of the FP32 and split
                 images (relative L2, PSLR / ISLR / SNR differences).
@@ -377,7 +378,8 @@ def serve_leg(args, torch, sar, dev):
            "workload": "Poisson arrivals, pool of 32 LFM scenes 1024^2..8192x16384 (seed 5), "
                        "5 targets, 20 dB; each request stages its scene into its own buffers"}
     n_req, n_warm = args.serve_requests, 100
-    for prec, budget_gib in (("fp32", 64), ("split_fp16", 64), ("fp32", 16)):
+    for prec, budget_gib in (("fp32", 64), ("split_fp16", 64), ("fp32_halfstore", 64),
+                             ("fp32", 16)):
         ex = GpuExecutor(4, budget_gib * GiB)
         srv = Server(budget_gib * GiB, slots=4, executor=ex, on_result=release_on_result)
         try:

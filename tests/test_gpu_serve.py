@@ -37,7 +37,7 @@ def test_served_equals_alone(slots):
     cfgs = pool()
     scenes = [simulate(c) for c in cfgs]
     raws = [dev(s.raw) for s in scenes]
-    precs = ["fp32", "split_fp16"]
+    precs = ["fp32", "split_fp16", "fp32_halfstore"]
     alone = {}
     for i, c in enumerate(cfgs):
         for p in precs:
@@ -48,7 +48,7 @@ def test_served_equals_alone(slots):
     _, which = poisson_arrivals(seed=21, n=60, rate_hz=5000.0, pool_size=len(cfgs))
     arrivals = np.cumsum(np.random.default_rng(21).exponential(1 / 5000.0, size=60))
     arrivals[:8] = 0.0                      # a burst first: requests must overlap
-    reqs = [(cfgs[w], raws[w], precs[k % 2]) for k, w in enumerate(which)]
+    reqs = [(cfgs[w], raws[w], precs[k % 3]) for k, w in enumerate(which)]
     budget = 2 * max(footprint_bytes(c) for c in cfgs)
     ex = GpuExecutor(slots, budget)
     srv = Server(budget, slots=slots, executor=ex, on_result=copy_out)
