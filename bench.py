@@ -82,6 +82,18 @@ def parse():
     return ap.parse_args()
 
 
+def cpu_model() -> str | None:
+    """The host CPU's model name (as lscpu reports it), if readable."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -561,7 +573,8 @@ def main():
         out["cpu_baseline"] = {"value": round(px / t / 1e6, 2), "unit": "Mpixel/s",
                                "cores": threads, "kind": "oracle",
                                "sample": "the full 4096x4096 headline scene once (FP64 "
-                                         f"oracle, compute only, {t:.2f} s)"}
+                                         f"oracle, compute only, {t:.2f} s)",
+                               "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
         out["accuracy_vs_oracle"] = accuracy(images, sc, ref, cfg)
     print(json.dumps(out))
 
