@@ -120,9 +120,11 @@ template <int N> struct LineLaunch {
 };
 
 // Minimum waves per SIMD requested for the line kernels: 4 for the FP32
-// 4096-point kernels (register reuse above), no request otherwise (the
-// split-precision kernels need more than 128 VGPRs).
-template <int N, int PREC> constexpr int line_wpe() { return (N == 4096 && PREC == 0) ? 4 : 1; }
+// 4096-point kernels (register reuse above); 2 for the split-precision
+// (MFMA) kernels, which need more than 128 VGPRs but left to themselves take
+// up to 268 (one wave per SIMD) for the fused 4096-point kernel; no request
+// otherwise.
+template <int N, int PREC> constexpr int line_wpe() { return (N == 4096 && PREC == 0) ? 4 : (PREC != 0 ? 2 : 1); }
 
 // Line transform in the requested butterfly precision: FP32 VALU passes, or
 // split FP16 / BF16 radix-16 passes on MFMA (twiddles and filters in FP32).
