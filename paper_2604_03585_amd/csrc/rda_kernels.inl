@@ -121,10 +121,13 @@ template <int N> struct LineLaunch {
 
 // Minimum waves per SIMD requested for the line kernels: 4 for the FP32
 // 4096-point kernels (register reuse above); 2 for the split-precision
-// (MFMA) kernels, which need more than 128 VGPRs but left to themselves take
-// up to 268 (one wave per SIMD) for the fused 4096-point kernel; no request
-// otherwise.
-template <int N, int PREC> constexpr int line_wpe() { return (N == 4096 && PREC == 0) ? 4 : (PREC != 0 ? 2 : 1); }
+// (MFMA) kernels (left to itself the fused 4096-point one takes 268 VGPRs,
+// one wave per SIMD); no request otherwise.
+template <int N, int PREC> constexpr int line_wpe()
+{
+    if constexpr (PREC == 0) return N == 4096 ? 4 : 1;
+    else return 2;     // four waves (128 VGPRs) spill in the split transforms, measured slower
+}
 
 // Line transform in the requested butterfly precision: FP32 VALU passes, or
 // split FP16 / BF16 radix-16 passes on MFMA (twiddles and filters in FP32).
