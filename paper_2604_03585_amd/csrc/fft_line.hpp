@@ -31,6 +31,18 @@
 
 namespace sar {
 
+// Workgroup barrier for LDS exchanges.  The compiler models the barrier and
+// its fences as side effects that do not write memory, so LDS reads issued
+// before a barrier may be sunk below it into a following branch, where they
+// race with other waves' writes of the next exchange.  The empty asm that
+// clobbers memory counts as a store and keeps every memory access on its
+// side of the barrier.
+__device__ __forceinline__ void wg_barrier()
+{
+    __syncthreads();
+    asm volatile("" ::: "memory");
+}
+
 // ---------------------------------------------------------------- complex
 __device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -288,7 +300,7 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[line_e(N)], float2* __restr
         }
     }
     if constexpr (!LAST) {
-        __syncthreads();
+        wg_barrier();
         if constexpr (SPLIT) {
             const float* re = (const float*)lds;
             const float* im = re + G::LDS;
@@ -299,13 +311,16 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[line_e(N)], float2* __restr
 #pragma unroll
             for (int m = 0; m < E; ++m) x[m] = lds[lds_pad(t + m * G::T)];
         }
-        __syncthreads();
+        wg_barrier();
     }
 }
 
-// Passes P.. of the line.  `before_last` runs just before the last pass
-// (callers use it to request data needed right after the transform, e.g.
-// the matched filter, so that its latency overlaps the last pass).
+// Passes P.. of the line.  `before_last` runs once the last pass's twiddle
+// loads are issued, just before its butterflies (callers use it to request
+// data needed after the transform, e.g. the matched filter, so that its
+// latency overlaps the last pass).  Vector-memory loads complete in issue
+// order, so a load issued ahead of the twiddles would hold up the pass; the
+// empty asm that clobbers memory keeps the callback's loads behind them.
 struct NoOp {
     __device__ __forceinline__ void operator()() const {}
 };
