@@ -317,11 +317,19 @@ __global__ __launch_bounds__(256) void k_corner_turn(const float2* __restrict__ 
 // Whole 64 x 64 tiles only (rows and cols multiples of 64): every global
 // access moves 16 bytes (two complex samples), half the instructions of
 // k_corner_turn.
+// LDS map: element (r, c) of the tile sits at column c ^ ((r >> 1) & 31) of
+// row r (no pad).  A bank holds 4 bytes and 64 banks span 32 samples, so a
+// sample's banks depend on its column mod 32.  The read phase has lane tx
+// take rows 2tx and 2tx+1 at one column c: the swizzle gives the 32 lanes
+// 32 different columns mod 32 (with a pad the even rows share 16), and the
+// 32 KiB tile lets five workgroups share a CU's LDS instead of four.
+__device__ __forceinline__ int turn_swz(int r, int c) { return c ^ ((r >> 1) & 31); }
+
 __global__ __launch_bounds__(256) void k_corner_turn_x2(const float4* __restrict__ in,
                                                         float4* __restrict__ out, int rows,
                                                         int cols)
 {
-    __shared__ float2 tile[TT][TT + 1];
+    __shared__ float2 tile[TT][TT];
     const int tiles_c = cols / TT;
     const int tr = blockIdx.x / tiles_c, tc = blockIdx.x % tiles_c;
     const int r0 = tr * TT, c0 = tc * TT;
@@ -331,14 +339,14 @@ __global__ __launch_bounds__(256) void k_corner_turn_x2(const float4* __restrict
     for (int i = 0; i < TT / 8; ++i) {
         const int r = ty + 8 * i;
         const float4 v = in[(size_t)(r0 + r) * cols2 + c0 / 2 + tx];
-        tile[r][2 * tx] = make_float2(v.x, v.y);
-        tile[r][2 * tx + 1] = make_float2(v.z, v.w);
+        tile[r][turn_swz(r, 2 * tx)] = make_float2(v.x, v.y);
+        tile[r][turn_swz(r, 2 * tx + 1)] = make_float2(v.z, v.w);
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < TT / 8; ++i) {
         const int c = ty + 8 * i;
-        const float2 a = tile[2 * tx][c], b = tile[2 * tx + 1][c];
+        const float2 a = tile[2 * tx][turn_swz(2 * tx, c)], b = tile[2 * tx + 1][turn_swz(2 * tx + 1, c)];
         out[(size_t)(c0 + c) * rows2 + r0 / 2 + tx] = make_float4(a.x, a.y, b.x, b.y);
     }
 }
@@ -372,8 +380,9 @@ __global__ __launch_bounds__(256) void k_corner_turn_b4(const uint2* __restrict_
 __global__ __launch_bounds__(256) void k_corner_turn_batch(const TurnTask* __restrict__ tasks,
                                                            int ntasks, int total_tiles)
 {
-    // every task is whole 64 x 64 tiles (plan sizes are powers of two >= 64)
-    __shared__ float2 tile[TT][TT + 1];
+    // every task is whole 64 x 64 tiles (plan sizes are powers of two >= 64);
+    // the tile's LDS map is k_corner_turn_x2's
+    __shared__ float2 tile[TT][TT];
     for (int gt = blockIdx.x; gt < total_tiles; gt += gridDim.x) {
         int lo = 0, hi = ntasks - 1;
         while (lo < hi) {
@@ -393,14 +402,15 @@ __global__ __launch_bounds__(256) void k_corner_turn_batch(const TurnTask* __res
         for (int i = 0; i < TT / 8; ++i) {
             const int r = ty + 8 * i;
             const float4 v = in[(size_t)(r0 + r) * cols2 + c0 / 2 + tx];
-            tile[r][2 * tx] = make_float2(v.x, v.y);
-            tile[r][2 * tx + 1] = make_float2(v.z, v.w);
+            tile[r][turn_swz(r, 2 * tx)] = make_float2(v.x, v.y);
+            tile[r][turn_swz(r, 2 * tx + 1)] = make_float2(v.z, v.w);
         }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < TT / 8; ++i) {
             const int c = ty + 8 * i;
-            const float2 a = tile[2 * tx][c], bb = tile[2 * tx + 1][c];
+            const float2 a = tile[2 * tx][turn_swz(2 * tx, c)];
+            const float2 bb = tile[2 * tx + 1][turn_swz(2 * tx + 1, c)];
             out[(size_t)(c0 + c) * rows2 + r0 / 2 + tx] = make_float4(a.x, a.y, bb.x, bb.y);
         }
         __syncthreads();
