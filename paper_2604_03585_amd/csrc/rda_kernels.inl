@@ -325,29 +325,60 @@ __global__ __launch_bounds__(256) void k_corner_turn(const float2* __restrict__ 
 // 32 KiB tile lets five workgroups share a CU's LDS instead of four.
 __device__ __forceinline__ int turn_swz(int r, int c) { return c ^ ((r >> 1) & 31); }
 
-__global__ __launch_bounds__(256) void k_corner_turn_x2(const float4* __restrict__ in,
-                                                        float4* __restrict__ out, int rows,
-                                                        int cols)
+// Tiles gt = blockIdx.x, + gridDim.x, ... (the launcher keeps gridDim.x <=
+// tiles): the next tile's loads are issued before the current tile leaves
+// LDS, so they overlap its stores; its LDS writes wait for those loads only
+// (vector-memory operations complete in issue order, the stores came after).
+// `more` is uniform per workgroup.
+__device__ __forceinline__ void turn_tile_to_lds(float2 (*tile)[TT], const float4 (&v)[TT / 8], int tx,
+                                                 int ty)
 {
-    __shared__ float2 tile[TT][TT];
-    const int tiles_c = cols / TT;
-    const int tr = blockIdx.x / tiles_c, tc = blockIdx.x % tiles_c;
-    const int r0 = tr * TT, c0 = tc * TT;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    const int cols2 = cols / 2, rows2 = rows / 2;
 #pragma unroll
     for (int i = 0; i < TT / 8; ++i) {
         const int r = ty + 8 * i;
-        const float4 v = in[(size_t)(r0 + r) * cols2 + c0 / 2 + tx];
-        tile[r][turn_swz(r, 2 * tx)] = make_float2(v.x, v.y);
-        tile[r][turn_swz(r, 2 * tx + 1)] = make_float2(v.z, v.w);
+        tile[r][turn_swz(r, 2 * tx)] = make_float2(v[i].x, v[i].y);
+        tile[r][turn_swz(r, 2 * tx + 1)] = make_float2(v[i].z, v[i].w);
     }
-    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_corner_turn_x2(const float4* __restrict__ in,
+                                                        float4* __restrict__ out, int rows,
+                                                        int cols, int tiles)
+{
+    __shared__ float2 tile[TT][TT];
+    const int tiles_c = cols / TT;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int cols2 = cols / 2, rows2 = rows / 2;
+    int gt = blockIdx.x;
+    float4 v[TT / 8];
+    {
+        const int r0 = (gt / tiles_c) * TT, c0 = (gt % tiles_c) * TT;
 #pragma unroll
-    for (int i = 0; i < TT / 8; ++i) {
-        const int c = ty + 8 * i;
-        const float2 a = tile[2 * tx][turn_swz(2 * tx, c)], b = tile[2 * tx + 1][turn_swz(2 * tx + 1, c)];
-        out[(size_t)(c0 + c) * rows2 + r0 / 2 + tx] = make_float4(a.x, a.y, b.x, b.y);
+        for (int i = 0; i < TT / 8; ++i) v[i] = in[(size_t)(r0 + ty + 8 * i) * cols2 + c0 / 2 + tx];
+    }
+    turn_tile_to_lds(tile, v, tx, ty);
+    wg_barrier();
+    for (;;) {
+        const int r0 = (gt / tiles_c) * TT, c0 = (gt % tiles_c) * TT;
+        const int next = gt + (int)gridDim.x;
+        const bool more = next < tiles;
+        if (more) {
+            const int nr0 = (next / tiles_c) * TT, nc0 = (next % tiles_c) * TT;
+#pragma unroll
+            for (int i = 0; i < TT / 8; ++i)
+                v[i] = in[(size_t)(nr0 + ty + 8 * i) * cols2 + nc0 / 2 + tx];
+        }
+#pragma unroll
+        for (int i = 0; i < TT / 8; ++i) {
+            const int c = ty + 8 * i;
+            const float2 a = tile[2 * tx][turn_swz(2 * tx, c)], b = tile[2 * tx + 1][turn_swz(2 * tx + 1, c)];
+            out[(size_t)(c0 + c) * rows2 + r0 / 2 + tx] = make_float4(a.x, a.y, b.x, b.y);
+        }
+        if (!more) break;
+        wg_barrier();                             // every read done before the next writes
+        turn_tile_to_lds(tile, v, tx, ty);
+        wg_barrier();
+        gt = next;
     }
 }
 
@@ -1629,9 +1660,14 @@ hipError_t launch_corner_turn(const void* in, void* out, int rows, int cols, hip
     if (tiles == 0) return hipSuccess;
     const bool whole = rows % TT == 0 && cols % TT == 0 &&
                        (((uintptr_t)in | (uintptr_t)out) & 15u) == 0;
-    if (whole)
-        hipLaunchKernelGGL(k_corner_turn_x2, dim3((unsigned)tiles), dim3(256), 0, s,
-                           (const float4*)in, (float4*)out, rows, cols);
+    if (whole) {
+        // a grid of at most 1280 workgroups (five per CU, as many as LDS
+        // holds), each taking the same number of tiles (the last round ragged)
+        const long long per = (tiles + 1279) / 1280;
+        const long long grid = (tiles + per - 1) / per;
+        hipLaunchKernelGGL(k_corner_turn_x2, dim3((unsigned)grid), dim3(256), 0, s,
+                           (const float4*)in, (float4*)out, rows, cols, (int)tiles);
+    }
     else
         hipLaunchKernelGGL(k_corner_turn, dim3((unsigned)tiles), dim3(256), 0, s,
                            (const float2*)in, (float2*)out, rows, cols);
