@@ -212,30 +212,35 @@ template <int N, int P> struct PassTw {
     float2 w[COUNT];
 };
 
+// TWP, radix-16 pass: W^1 and W^4 come from the table, the other powers are
+// products (at most four roundings deep, ~3e-7 relative).  Thirteen complex
+// products replace thirteen table reads, for kernels bound by vector-memory
+// issue rather than by VALU.  w[i-1] = W^i, w[0] and w[3] given.
+__device__ __forceinline__ void tw_products16(float2* w)
+{
+    w[1] = c_mul(w[0], w[0]);
+    w[2] = c_mul(w[1], w[0]);
+    w[4] = c_mul(w[3], w[0]);
+    w[5] = c_mul(w[3], w[1]);
+    w[6] = c_mul(w[3], w[2]);
+    w[7] = c_mul(w[3], w[3]);
+#pragma unroll
+    for (int i = 8; i < 15; ++i) w[i] = c_mul(w[7], w[i - 8]);
+}
+
 template <int N, int P, bool TWP>
 __device__ __forceinline__ void load_tw(PassTw<N, P>& pt, const float2* __restrict__ tw, int t)
 {
     using G = LineGeom<N>;
     if constexpr (TWP && PassTw<N, P>::ANY && G::radix(P) == 16) {
-        // TWP, radix-16 pass: W^1 and W^4 come from the table, the other
-        // powers are products (at most four roundings deep, ~3e-7 relative).
-        // Thirteen complex products replace thirteen table reads, for kernels
-        // bound by vector-memory issue rather than by VALU.
         constexpr int NS = G::span(P), B = line_e(N) / 16, OFF = G::tw_off(P);
 #pragma unroll
         for (int q = 0; q < B; ++q) {
             const int jm = (t + q * G::T) & (NS - 1);
-            float2* w = pt.w + q * 15;          // w[i-1] = W^i
+            float2* w = pt.w + q * 15;
             w[0] = tw[OFF + jm];
             w[3] = tw[OFF + 3 * NS + jm];
-            w[1] = c_mul(w[0], w[0]);
-            w[2] = c_mul(w[1], w[0]);
-            w[4] = c_mul(w[3], w[0]);
-            w[5] = c_mul(w[3], w[1]);
-            w[6] = c_mul(w[3], w[2]);
-            w[7] = c_mul(w[3], w[3]);
-#pragma unroll
-            for (int i = 8; i < 15; ++i) w[i] = c_mul(w[7], w[i - 8]);
+            tw_products16(w);
         }
     } else if constexpr (PassTw<N, P>::ANY) {
         constexpr int R = G::radix(P), NS = G::span(P), B = line_e(N) / R, OFF = G::tw_off(P);
@@ -245,6 +250,47 @@ __device__ __forceinline__ void load_tw(PassTw<N, P>& pt, const float2* __restri
 #pragma unroll
             for (int i = 1; i < R; ++i) pt.w[q * (R - 1) + i - 1] = tw[OFF + (i - 1) * NS + jm];
         }
+    }
+}
+
+// The table reads of a TWP radix-16 pass (W^1, W^4 per butterfly), issued
+// one pass ahead so that their latency overlaps the previous pass and its
+// LDS exchange; other passes read their twiddles when they start.
+template <int N, int P, bool TWP> struct TwAhead {
+    static constexpr bool ON = TWP && PassTw<N, P>::ANY && LineGeom<N>::radix(P) == 16;
+    static constexpr int B = ON ? line_e(N) / 16 : 1;
+    float2 w1[B], w4[B];
+};
+
+template <int N, int P, bool TWP>
+__device__ __forceinline__ void tw_issue(TwAhead<N, P, TWP>& a, const float2* __restrict__ tw, int t)
+{
+    if constexpr (TwAhead<N, P, TWP>::ON) {
+        using G = LineGeom<N>;
+        constexpr int NS = G::span(P), OFF = G::tw_off(P);
+#pragma unroll
+        for (int q = 0; q < TwAhead<N, P, TWP>::B; ++q) {
+            const int jm = (t + q * G::T) & (NS - 1);
+            a.w1[q] = tw[OFF + jm];
+            a.w4[q] = tw[OFF + 3 * NS + jm];
+        }
+    }
+}
+
+template <int N, int P, bool TWP>
+__device__ __forceinline__ void tw_form(PassTw<N, P>& pt, const TwAhead<N, P, TWP>& a,
+                                        const float2* __restrict__ tw, int t)
+{
+    if constexpr (TwAhead<N, P, TWP>::ON) {
+#pragma unroll
+        for (int q = 0; q < TwAhead<N, P, TWP>::B; ++q) {
+            float2* w = pt.w + q * 15;
+            w[0] = a.w1[q];
+            w[3] = a.w4[q];
+            tw_products16(w);
+        }
+    } else {
+        load_tw<N, P, TWP>(pt, tw, t);
     }
 }
 
@@ -325,16 +371,26 @@ struct NoOp {
     __device__ __forceinline__ void operator()() const {}
 };
 
-template <int N, bool INV, bool TWP, int P, bool SPLIT, class F>
+// AHEAD: a TWP radix-16 pass's table reads are issued one pass early (they
+// cost four registers across the previous pass, which the fused kernels
+// cannot spare; the forward / inverse-only kernels can).
+template <int N, bool INV, bool TWP, int P, bool SPLIT, bool AHEAD, class F>
 __device__ __forceinline__ void fft_from(float2 (&x)[line_e(N)], float2* __restrict__ lds,
-                                         const float2* __restrict__ tw, int t, F&& before_last)
+                                         const float2* __restrict__ tw, int t, F&& before_last,
+                                         const TwAhead<N, P, TWP>& ahead)
 {
     if constexpr (P < LineGeom<N>::NP) {
         if constexpr (P == LineGeom<N>::NP - 1) before_last();
         PassTw<N, P> cur;
-        load_tw<N, P, TWP>(cur, tw, t);
+        TwAhead<N, P + 1, TWP> next;
+        if constexpr (AHEAD) {
+            tw_form<N, P, TWP>(cur, ahead, tw, t);
+            tw_issue<N, P + 1, TWP>(next, tw, t);
+        } else {
+            load_tw<N, P, TWP>(cur, tw, t);
+        }
         fft_pass<N, P, INV, SPLIT>(x, lds, cur, t);
-        fft_from<N, INV, TWP, P + 1, SPLIT>(x, lds, tw, t, before_last);
+        fft_from<N, INV, TWP, P + 1, SPLIT, AHEAD>(x, lds, tw, t, before_last, next);
     }
 }
 
@@ -344,7 +400,19 @@ template <int N, bool INV, bool TWP = true, bool SPLIT = false, class F = NoOp>
 __device__ __forceinline__ void fft_line(float2 (&x)[line_e(N)], float2* __restrict__ lds,
                                          const float2* __restrict__ tw, int t, F&& before_last = F())
 {
-    fft_from<N, INV, TWP, 0, SPLIT>(x, lds, tw, t, before_last);
+    TwAhead<N, 0, TWP> first;
+    fft_from<N, INV, TWP, 0, SPLIT, false>(x, lds, tw, t, before_last, first);
+}
+
+// The same transform with every TWP radix-16 pass's table reads issued one
+// pass ahead (no last-pass hook).
+template <int N, bool INV, bool TWP = true, bool SPLIT = false>
+__device__ __forceinline__ void fft_line_ahead(float2 (&x)[line_e(N)], float2* __restrict__ lds,
+                                               const float2* __restrict__ tw, int t)
+{
+    TwAhead<N, 0, TWP> first;
+    tw_issue<N, 0, TWP>(first, tw, t);
+    fft_from<N, INV, TWP, 0, SPLIT, true>(x, lds, tw, t, NoOp(), first);
 }
 
 }  // namespace sar

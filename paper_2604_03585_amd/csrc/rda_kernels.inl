@@ -131,12 +131,16 @@ template <int N, int PREC> constexpr int line_wpe()
 
 // Line transform in the requested butterfly precision: FP32 VALU passes, or
 // split FP16 / BF16 radix-16 passes on MFMA (twiddles and filters in FP32).
-template <int N, bool INV, int PREC, bool TWP = true, bool SPLIT = false, class F = NoOp>
+template <int N, bool INV, int PREC, bool TWP = true, bool SPLIT = false, class F = NoOp,
+          bool AHEAD = false>
 __device__ __forceinline__ void fft_any(float2 (&x)[line_e(N)], float2* __restrict__ lds,
                                         const float2* __restrict__ tw, int sub, int t,
                                         F&& before_last = F())
 {
-    if constexpr (PREC == PREC_FP32) {
+    if constexpr (PREC == PREC_FP32 && AHEAD) {
+        before_last();
+        fft_line_ahead<N, INV, TWP, SPLIT>(x, lds, tw, t);
+    } else if constexpr (PREC == PREC_FP32) {
         fft_line<N, INV, TWP, SPLIT>(x, lds, tw, t, before_last);
     } else {
         using L = LineLaunch<N>;
@@ -210,7 +214,7 @@ __device__ __forceinline__ void line_group(const float2* in, float2* out, int li
         if constexpr (L::RECOMPUTE_INV_TW) asm volatile("" : "+v"(ti));   // hide ti == t
         fft_any<N, true, PREC, TWP>(x, lds, tw, sub, ti);
     } else {
-        fft_any<N, KIND == LK_INV, PREC, TWP, SPLIT>(x, lds, tw, sub, t);
+        fft_any<N, KIND == LK_INV, PREC, TWP, SPLIT, NoOp, true>(x, lds, tw, sub, t);
         if (scale != 1.0f) {
 #pragma unroll
             for (int m = 0; m < E; ++m) x[m] = c_scale(x[m], scale);
