@@ -988,9 +988,9 @@ k_rcmc_az2(const void* __restrict__ A_, float2* __restrict__ out, RcmcArgs ra,
             rcmc_rows2<N, true, line_e(N), LineGeom<N>::T, SrcT>(xa, xb, A, ra, n, t, tab);
     }
     __syncthreads();                              // table reads done before LDS reuse
-    fft_any<N, true, PREC>(xa, lds, tw, sub, t);
+    fft_any<N, true, PREC, true, false, NoOp, true>(xa, lds, tw, sub, t);
     if (live) store_line<N>(xa, out + (size_t)n * N, t);
-    fft_any<N, true, PREC>(xb, lds, tw, sub, t);
+    fft_any<N, true, PREC, true, false, NoOp, true>(xb, lds, tw, sub, t);
     if (live) store_line<N>(xb, out + (size_t)(n + 1) * N, t);
 }
 
