@@ -405,14 +405,15 @@ __device__ __forceinline__ void fft_line(float2 (&x)[line_e(N)], float2* __restr
 }
 
 // The same transform with every TWP radix-16 pass's table reads issued one
-// pass ahead (no last-pass hook).
-template <int N, bool INV, bool TWP = true, bool SPLIT = false>
+// pass ahead.
+template <int N, bool INV, bool TWP = true, bool SPLIT = false, class F = NoOp>
 __device__ __forceinline__ void fft_line_ahead(float2 (&x)[line_e(N)], float2* __restrict__ lds,
-                                               const float2* __restrict__ tw, int t)
+                                               const float2* __restrict__ tw, int t,
+                                               F&& before_last = F())
 {
     TwAhead<N, 0, TWP> first;
     tw_issue<N, 0, TWP>(first, tw, t);
-    fft_from<N, INV, TWP, 0, SPLIT, true>(x, lds, tw, t, NoOp(), first);
+    fft_from<N, INV, TWP, 0, SPLIT, true>(x, lds, tw, t, before_last, first);
 }
 
 }  // namespace sar

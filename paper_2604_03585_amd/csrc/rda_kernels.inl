@@ -138,8 +138,7 @@ __device__ __forceinline__ void fft_any(float2 (&x)[line_e(N)], float2* __restri
                                         F&& before_last = F())
 {
     if constexpr (PREC == PREC_FP32 && AHEAD) {
-        before_last();
-        fft_line_ahead<N, INV, TWP, SPLIT>(x, lds, tw, t);
+        fft_line_ahead<N, INV, TWP, SPLIT>(x, lds, tw, t, before_last);
     } else if constexpr (PREC == PREC_FP32) {
         fft_line<N, INV, TWP, SPLIT>(x, lds, tw, t, before_last);
     } else {
@@ -203,16 +202,20 @@ __device__ __forceinline__ void line_group(const float2* in, float2* out, int li
     }
     if constexpr (KIND == LK_FUSED) {
         // the filter is requested just before the last forward pass
+        // lines of 8192 points and more (one or two workgroups per CU) read
+        // their twiddles one pass ahead; shorter ones have no registers for it
+        constexpr bool AHEAD = N >= 8192;
         float2 h[E];
-        fft_any<N, false, PREC, TWP>(x, lds, tw, sub, t, [&] {
+        auto filter = [&] {
 #pragma unroll
             for (int m = 0; m < E; ++m) h[m] = H[t + m * L::T];
-        });
+        };
+        fft_any<N, false, PREC, TWP, false, decltype(filter)&, AHEAD>(x, lds, tw, sub, t, filter);
 #pragma unroll
         for (int m = 0; m < E; ++m) x[m] = c_mul(x[m], h[m]);
         int ti = t;
         if constexpr (L::RECOMPUTE_INV_TW) asm volatile("" : "+v"(ti));   // hide ti == t
-        fft_any<N, true, PREC, TWP>(x, lds, tw, sub, ti);
+        fft_any<N, true, PREC, TWP, false, NoOp, AHEAD>(x, lds, tw, sub, ti);
     } else {
         fft_any<N, KIND == LK_INV, PREC, TWP, SPLIT, NoOp, true>(x, lds, tw, sub, t);
         if (scale != 1.0f) {
