@@ -1156,20 +1156,24 @@ k_line_hs(const void* __restrict__ in, void* __restrict__ out, int lines,
 #pragma unroll
         for (int m = 0; m < E; ++m) x[m] = make_float2(0.f, 0.f);
     }
+    // twiddle reads one pass ahead where registers allow, as in line_group
     if constexpr (KIND == LK_FUSED) {
         float2 h[E];
-        fft_line<N, false>(x, lds, tw, t, [&] {
+        auto filter = [&] {
 #pragma unroll
             for (int m = 0; m < E; ++m) h[m] = H[t + m * L::T];
-        });
+        };
+        if constexpr (N >= 8192) fft_line_ahead<N, false>(x, lds, tw, t, filter);
+        else fft_line<N, false>(x, lds, tw, t, filter);
 #pragma unroll
         for (int m = 0; m < E; ++m) x[m] = c_mul(x[m], h[m]);
         int ti = t;
         if constexpr (L::RECOMPUTE_INV_TW) asm volatile("" : "+v"(ti));
-        fft_line<N, true>(x, lds, tw, ti);
+        if constexpr (N >= 8192) fft_line_ahead<N, true>(x, lds, tw, ti);
+        else fft_line<N, true>(x, lds, tw, ti);
     } else {
         static_assert(KIND == LK_FWD, "fused or forward");
-        fft_line<N, false>(x, lds, tw, t);
+        fft_line_ahead<N, false>(x, lds, tw, t);
     }
     if constexpr (OUT_H) {
         const int e = half_exponent(line_absmax<N>(x, (float*)smem, sub));
