@@ -361,19 +361,18 @@ __device__ __forceinline__ void fft_pass(float2 (&x)[line_e(N)], float2* __restr
     }
 }
 
-// Passes P.. of the line.  `before_last` runs once the last pass's twiddle
-// loads are issued, just before its butterflies (callers use it to request
-// data needed after the transform, e.g. the matched filter, so that its
-// latency overlaps the last pass).  Vector-memory loads complete in issue
-// order, so a load issued ahead of the twiddles would hold up the pass; the
-// empty asm that clobbers memory keeps the callback's loads behind them.
+// Passes P.. of the line.  `before_last` runs just before the last pass
+// (callers use it to request data needed right after the transform, e.g.
+// the matched filter, so that its latency overlaps the last pass).
 struct NoOp {
     __device__ __forceinline__ void operator()() const {}
 };
 
-// AHEAD: a TWP radix-16 pass's table reads are issued one pass early (they
-// cost four registers across the previous pass, which the fused kernels
-// cannot spare; the forward / inverse-only kernels can).
+// AHEAD: a TWP radix-16 pass's table reads are issued one pass early, so
+// they are in flight during the previous pass and its exchange (and, for
+// the last pass, ahead of the `before_last` loads).  They cost four
+// registers across the previous pass: the forward / inverse-only, RCMC and
+// long-line fused kernels have them, the shorter fused kernels do not.
 template <int N, bool INV, bool TWP, int P, bool SPLIT, bool AHEAD, class F>
 __device__ __forceinline__ void fft_from(float2 (&x)[line_e(N)], float2* __restrict__ lds,
                                          const float2* __restrict__ tw, int t, F&& before_last,
