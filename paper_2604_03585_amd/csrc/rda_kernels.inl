@@ -201,16 +201,19 @@ __device__ __forceinline__ void line_group(const float2* in, float2* out, int li
         for (int m = 0; m < E; ++m) x[m] = make_float2(0.f, 0.f);
     }
     if constexpr (KIND == LK_FUSED) {
-        // the filter is requested just before the last forward pass
-        // lines of 8192 points and more (one or two workgroups per CU) read
-        // their twiddles one pass ahead; shorter ones have no registers for it
+        // the filter is requested just before the last forward pass.  Lines
+        // of 8192 points and more (one or two workgroups per CU) read their
+        // twiddles one pass ahead in both transforms, 4096-point lines in the
+        // forward one (in the inverse too they spill), shorter ones not at
+        // all (registers)
         constexpr bool AHEAD = N >= 8192;
+        constexpr bool AHEAD_FWD = AHEAD || N == 4096;
         float2 h[E];
         auto filter = [&] {
 #pragma unroll
             for (int m = 0; m < E; ++m) h[m] = H[t + m * L::T];
         };
-        fft_any<N, false, PREC, TWP, false, decltype(filter)&, AHEAD>(x, lds, tw, sub, t, filter);
+        fft_any<N, false, PREC, TWP, false, decltype(filter)&, AHEAD_FWD>(x, lds, tw, sub, t, filter);
 #pragma unroll
         for (int m = 0; m < E; ++m) x[m] = c_mul(x[m], h[m]);
         int ti = t;
