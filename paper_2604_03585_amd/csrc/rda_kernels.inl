@@ -1160,13 +1160,14 @@ k_line_hs(const void* __restrict__ in, void* __restrict__ out, int lines,
         for (int m = 0; m < E; ++m) x[m] = make_float2(0.f, 0.f);
     }
     // twiddle reads one pass ahead where registers allow, as in line_group
+    // (fused: forward from 4096 points, inverse from 8192)
     if constexpr (KIND == LK_FUSED) {
         float2 h[E];
         auto filter = [&] {
 #pragma unroll
             for (int m = 0; m < E; ++m) h[m] = H[t + m * L::T];
         };
-        if constexpr (N >= 8192) fft_line_ahead<N, false>(x, lds, tw, t, filter);
+        if constexpr (N >= 4096) fft_line_ahead<N, false>(x, lds, tw, t, filter);
         else fft_line<N, false>(x, lds, tw, t, filter);
 #pragma unroll
         for (int m = 0; m < E; ++m) x[m] = c_mul(x[m], h[m]);
