@@ -176,7 +176,8 @@ int orc_corner_turn(const double* in, int rows, int cols, double* out)
 /*   w_t(x) = K(t - x) / sum_t' K(t' - x).                             */
 /* Pinned: I0 against known values and an independent library; x = 0  */
 /* gives the identity; weights sum to 1; fractional shift of a         */
-/* band-limited tone.                                                  */
+/* band-limited tone; the normalised weights at x = 1/10, 1/4, 1/2,    */
+/* 3/4 against a library Kaiser window times a library sinc.           */
 /* ------------------------------------------------------------------ */
 double orc_bessel_i0(double y)
 {
@@ -200,7 +201,9 @@ static double kaiser_sinc(double z, double beta, double half)
 {
     if (fabs(z) > half) return 0.0;
     double r = z / half;
-    return sinc(z) * orc_bessel_i0(beta * sqrt(1.0 - r * r)) / orc_bessel_i0(beta);
+    double b = MUT(13) ? 2.0 * beta : (MUT(15) ? 0.0 : beta);
+    double s = MUT(14) ? sqrt(1.0 - fabs(r)) : sqrt(1.0 - r * r);
+    return sinc(z) * orc_bessel_i0(b * s) / orc_bessel_i0(b);
 }
 
 /* w[0..taps-1] for t = -(taps/2 - 1) .. taps/2. */

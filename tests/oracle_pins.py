@@ -249,6 +249,28 @@ def pin_rcmc_weights_structure():
     assert abs(w[3] - w[4]) < 1e-15 and w[3] == np.max(w)
 
 
+def pin_rcmc_weights_kaiser_values():
+    """The normalised weights themselves, against an independent construction:
+    scipy's Kaiser window (its own I0) times numpy's sinc, normalised to unit
+    sum.  A symmetric Kaiser window of M = 2*4*D + 1 points spans offsets
+    -4 .. 4 in steps of 1/D, so tap t = -3 .. 4 at fractional position x = c/D
+    sits on window node (t - x)*D + 4*D.  x = 1/10, 1/4, 1/2 and 3/4 hit the
+    nodes exactly; beta = 2.5, half-width 4 (Sec. IV.A step 3, our reading of
+    the 8-tap sinc interpolator).  Catches a wrong beta, a wrong window shape
+    (e.g. sqrt(1 - |r|)), a missing window or a wrong tap alignment."""
+    from scipy.signal.windows import kaiser
+    beta, half = 2.5, 4
+    taps = np.arange(-3, 5)
+    for num, den in ((1, 10), (1, 4), (1, 2), (3, 4)):
+        x = num / den
+        win = kaiser(2 * half * den + 1, beta, sym=True)
+        nodes = (taps * den - num) + half * den
+        ref = np.sinc(taps - x) * win[nodes]
+        ref = ref / np.sum(ref)
+        got = O.rcmc_weights(x)
+        assert np.max(np.abs(got - ref)) < 1e-12, (x, np.max(np.abs(got - ref)))
+
+
 def pin_rcmc_weights_interpolate_tones():
     """A band-limited tone exp(2 pi j f i), |f| <= 0.3, interpolated at
     fractional positions matches the analytic tone within the passband ripple
@@ -345,6 +367,7 @@ ALL_PINS = [
     pin_noise_gain,
     pin_bessel_i0,
     pin_rcmc_weights_structure,
+    pin_rcmc_weights_kaiser_values,
     pin_rcmc_weights_interpolate_tones,
     pin_rcmc_pulse_returns_to_r0,
     pin_rcmc_disabled_is_phase_only,

@@ -6,13 +6,15 @@ must fail at least one pin.  Mistakes (oracle_rda.c, MUT(k)):
  4 matched filter not conjugated  10 azimuth phase sign flipped
  5 replica off-centre by a sample 11 I0 series with k! instead of k!^2
  6 corner turn writes untransposed 12 Doppler bins not in fftfreq order
+13 Kaiser window with 2*beta       14 window sqrt(1 - |r|) instead of sqrt(1 - r^2)
+15 window dropped (beta = 0, a truncated sinc)
 """
 import pytest
 
 import oracle_pins as P
 from oracle import oracle as O
 
-MUTANTS = list(range(1, 13))
+MUTANTS = list(range(1, 16))
 
 
 @pytest.fixture(scope="module")
