@@ -121,11 +121,15 @@ typedef struct {
     int32_t  precision, schedule, transpose_back;
 } sar_params;
 
-/* Build a plan: validates `p`, allocates the plan's device tables and fills
+/* Build a plan (Sec. II.B: the matched filter is pre-computed once, outside
+ * the per-line pipeline; Sec. II.C: the IFFT's 1/N scale is applied once, here
+ * folded into the filter; Sec. IV.A: the filters H_r and H_a(f_a, R0) and the
+ * RCMC geometry).  Validates `p`, allocates the plan's device tables and fills
  * them on `stream` with FP64 generator kernels (twiddles exp(-2 pi i k/N),
  * the matched filters with the IFFT's 1/N folded in, and for the hyperbolic
  * model the per-Doppler-bin RCMC stretch 1/D-1 and phase rate 2D/lambda).
- * Synchronises `stream` before returning.  *out receives the plan. */
+ * Synchronises `stream` before returning.  *out receives the plan; on any
+ * error *out is left NULL and nothing stays allocated. */
 sar_status sar_plan(const sar_params* p, void* stream, sar_plan_t* out);
 
 /* Free a plan.  The caller must have synchronised every stream that used it. */

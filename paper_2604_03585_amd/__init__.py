@@ -48,18 +48,41 @@ class Plan:
 
     def execute(self, raw, out=None, work=None, stream=None):
         """raw: complex64 CUDA tensor (Na, Nr) -> image tensor ((Nr, Na), or
-        (Na, Nr) with transpose_back).  Asynchronous on ``stream``."""
+        (Na, Nr) with transpose_back).  Asynchronous on ``stream`` (default:
+        the current stream).  ``out`` and ``work`` are checked for device,
+        dtype, contiguity and size; temporaries are allocated on ``stream``."""
         import torch
         if raw.dtype != torch.complex64 or not raw.is_cuda or not raw.is_contiguous():
             raise ValueError("raw must be a contiguous complex64 CUDA tensor")
         if tuple(raw.shape) != (self.Na, self.Nr):
             raise ValueError(f"raw has shape {tuple(raw.shape)}, plan wants {(self.Na, self.Nr)}")
-        if out is None:
-            out = torch.empty(self.image_shape(), dtype=torch.complex64, device=raw.device)
-        if work is None:
-            work = torch.empty(((self.workspace_bytes + 7) // 8,), dtype=torch.complex64,
-                               device=raw.device)
-        sar_rda_execute(self.handle, raw, out, work, stream)
+        if out is not None:
+            if (out.dtype != torch.complex64 or out.device != raw.device
+                    or not out.is_contiguous() or tuple(out.shape) != self.image_shape()):
+                raise ValueError(f"out must be a contiguous complex64 tensor of shape "
+                                 f"{self.image_shape()} on {raw.device}")
+        if work is not None:
+            if (work.device != raw.device or not work.is_contiguous()
+                    or work.numel() * work.element_size() < self.workspace_bytes):
+                raise ValueError(f"work must be a contiguous tensor of at least "
+                                 f"{self.workspace_bytes} bytes on {raw.device}")
+        if stream is None:
+            s = torch.cuda.current_stream(raw.device)
+        elif isinstance(stream, torch.cuda.Stream):
+            s = stream
+        else:   # a raw hipStream_t handle
+            s = torch.cuda.ExternalStream(int(stream), device=raw.device)
+        with torch.cuda.stream(s):
+            # allocated on `s`: the caching allocator will not hand these
+            # blocks to other streams while the kernels below may use them
+            if out is None:
+                out = torch.empty(self.image_shape(), dtype=torch.complex64, device=raw.device)
+            tmp = None
+            if work is None:
+                tmp = work = torch.empty(((self.workspace_bytes + 7) // 8,),
+                                         dtype=torch.complex64, device=raw.device)
+            sar_rda_execute(self.handle, raw, out, work, s)
+            del tmp
         return out
 
     def close(self):

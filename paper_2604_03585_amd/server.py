@@ -184,6 +184,7 @@ class Request:
     arrival: float
     blocks: tuple
     future: cf.Future
+    ready: object = None        # executor's marker: raw's producer has finished
     admitted: float = 0.0
     img_off: int = -1
     scratch_off: int = -1
@@ -244,6 +245,10 @@ class Server:
         fut: cf.Future = cf.Future()
         now = time.perf_counter()
         blocks = scene_blocks(cfg)
+        # taken in the caller's thread, on the caller's current stream: work
+        # the client queued to fill raw is ordered before the request's copy
+        prepare = getattr(self.executor, "prepare", None)
+        ready = prepare(raw) if prepare is not None else None
         with self._lock:
             if self._closing:
                 raise ServerError("server is closed")
@@ -254,7 +259,7 @@ class Server:
                 fut.set_exception(ServerError(
                     f"request {rid}: footprint {need} bytes exceeds the HBM budget {self.budget}"))
                 return fut
-            self._queue.append(Request(rid, cfg, raw, precision, now, blocks, fut))
+            self._queue.append(Request(rid, cfg, raw, precision, now, blocks, fut, ready))
             self._wake.notify()
         return fut
 
@@ -416,6 +421,16 @@ class GpuExecutor:
         n = int(np.prod(shape))
         return self.arena[off:off + 8 * n].view(self.torch.complex64).view(shape)
 
+    def prepare(self, raw):
+        """Called by submit() in the client's thread: an event on the client's
+        current stream, after whatever work the client queued to produce
+        ``raw`` (e.g. a non-blocking host-to-device copy)."""
+        if raw is None or not getattr(raw, "is_cuda", False):
+            return None
+        ev = self.torch.cuda.Event()
+        ev.record(self.torch.cuda.current_stream(raw.device))
+        return ev
+
     def launch(self, req: Request, slot: int):
         from ._lib import sar_rda_execute
         s = self.streams[slot]
@@ -425,6 +440,10 @@ class GpuExecutor:
         raw = self._view(req.scratch_off, (p.Na, p.Nr))
         work = self._view(req.scratch_off + 8 * px, ((p.workspace_bytes + 7) // 8,))
         with self.torch.cuda.stream(s):
+            if req.ready is not None:
+                s.wait_event(req.ready)                 # raw's producer first
+            if getattr(req.raw, "is_cuda", False):
+                req.raw.record_stream(s)                # keep raw's memory until the copy ran
             raw.copy_(req.raw, non_blocking=True)       # stage into the request's buffer
             sar_rda_execute(p.handle, raw, img, work, s)
             ev = self.torch.cuda.Event()

@@ -82,3 +82,33 @@ def test_served_fp32_matches_oracle():
         r.release()
     assert srv.used_bytes == 0
     srv.executor.close()
+
+
+def test_submit_orders_copy_after_client_stream():
+    """A client fills raw asynchronously on its own stream (a delay, then a
+    non-blocking copy from pinned host memory) and submits at once: the
+    request's staging copy must wait for that work, so the served image is
+    the image of the scene, not of the buffer's earlier contents."""
+    torch = torch_cuda()
+    cfg = pool()[3]
+    sc = simulate(cfg)
+    with sar.Plan(cfg) as plan:
+        want = host(plan.execute(dev(sc.raw)))
+    pinned = torch.from_numpy(sc.raw).pin_memory()
+    raw = torch.zeros(pinned.shape, dtype=torch.complex64, device="cuda")
+    torch.cuda.synchronize()
+    producer = torch.cuda.Stream()
+    srv = Server(1 << 30, slots=2)
+    try:
+        with torch.cuda.stream(producer):
+            if hasattr(torch.cuda, "_sleep"):
+                torch.cuda._sleep(20_000_000)       # ~10 ms of device time first
+            raw.copy_(pinned, non_blocking=True)
+            fut = srv.submit(cfg, raw)
+        res = fut.result(60)
+        got = host(res.image)
+        res.release()
+    finally:
+        srv.close()
+    assert np.array_equal(got, want)
+    srv.executor.close()
