@@ -15,11 +15,19 @@
 //
 // Each FP32 operand is split as x = hi + lo (hi = round(x), lo =
 // round(x - hi)) and the product is accumulated in FP32 as
-// F_hi X_hi + F_hi X_lo + F_lo X_hi (the lo*lo term is dropped).  F carries a
-// factor 1/16 (exact) so that FP16 never overflows: values shrink by at most
-// the DFT's gain; the caller restores 16^passes at the end.  Twiddles are
-// applied in FP32 between passes, on the output side of a pass (where a lane
-// holds complete complex values), already for the next pass.
+// F_hi X_hi + F_hi X_lo + F_lo X_hi (the lo*lo term is dropped).
+//
+// Range.  FP16 holds magnitudes up to 65504, and its lo parts keep full
+// precision only while |x| >= 2^-3 (below that they go subnormal).  So every
+// line is first scaled by a power of two 2^-e of its own (exact), chosen from
+// the line's largest component so that it lies in [2^14, 2^15).  F carries a
+// factor 1/16 (exact): then |Y_k| = |sum_n F[k][n] x_n| <= max_n |x_n| for
+// every output of a pass, and the twiddles keep magnitudes, so no component
+// ever exceeds sqrt(2) * 2^15 < 65504 whatever the input's scale; the
+// transform's values stay within the line's own dynamic range of 2^15.  The
+// scale 2^e * 16^passes is restored at the end.  Twiddles are applied in
+// FP32 between passes, on the output side of a pass (where a lane holds
+// complete complex values), already for the next pass.
 //
 // LDS holds the WG's lines in split form: re[] then im[], one pad slot per 16
 // entries, the same bytes as the float2 layout of the FP32 path.
@@ -105,6 +113,46 @@ __device__ __forceinline__ DftOperands<PREC> dft16_operands(int lane)
 
 __device__ __forceinline__ int mf_pad(int i) { return i + (i >> 4); }
 
+// Exponent e of a line whose largest component is amax: amax * 2^-e lies in
+// [2^14, 2^15); zero, non-finite and empty lines keep e = 0.
+__device__ __forceinline__ int mfma_line_exponent(float amax)
+{
+    if (!(amax > 0.f) || !(amax < INFINITY)) return 0;
+    return max(ilogbf(amax) - 14, -126);
+}
+
+// The line's exponent, from the largest |re|, |im| over its T threads: lane
+// segments of a wave when T <= 64, else whole waves combined through the
+// line's LDS pad slots (entries 17 w + 16 of its re[] array, which the passes
+// never touch since mf_pad skips them).  On entry no wave may still read the
+// workgroup's LDS (the callers end every earlier LDS use with a barrier).
+template <int T, int LL>
+__device__ __forceinline__ int mfma_line_scale_exp(const float2 (&x)[16], float* __restrict__ re,
+                                                   int sub)
+{
+    float m = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) m = fmaxf(m, fmaxf(fabsf(x[i].x), fabsf(x[i].y)));
+    constexpr int W = T < 64 ? T : 64;
+#pragma unroll
+    for (int off = 1; off < W; off <<= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if constexpr (T > 64) {
+        constexpr int WPL = T / 64;               // waves per line
+        static_assert(17 * (WPL - 1) + 16 < LL, "pad slots of the line");
+        const int lane = threadIdx.x & 63, wl = (threadIdx.x >> 6) % WPL;
+        float* slots = re + sub * LL;
+        if (lane == 0) slots[17 * wl + 16] = m;
+        __syncthreads();
+        m = 0.f;
+#pragma unroll
+        for (int w = 0; w < WPL; ++w) m = fmaxf(m, slots[17 * w + 16]);
+    }
+    const int e = mfma_line_exponent(m);
+    // a wave holds one line when T >= 64: the exponent is wave-uniform
+    if constexpr (T >= 64) return __builtin_amdgcn_readfirstlane(e);
+    else return e;
+}
+
 // All radix-16 passes of the lines of one workgroup on MFMA, followed by the
 // trailing smaller pass (if any) in FP32.  On entry each thread holds its
 // line's x in the strided register layout (see fft_line.hpp); on exit it
@@ -129,12 +177,13 @@ __device__ __forceinline__ void fft_line_mfma(float2 (&x)[16], float* __restrict
     float* re = lds;
     float* im = lds + LPW * LL;
 
-    // registers -> LDS (split)
+    // registers -> LDS (split), scaled by the line's 2^-ex
+    const int ex = mfma_line_scale_exp<T, LL>(x, re, sub);
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
         const int e = sub * LL + mf_pad(t + m * T);
-        re[e] = x[m].x;
-        im[e] = x[m].y;
+        re[e] = ldexpf(x[m].x, -ex);
+        im[e] = ldexpf(x[m].y, -ex);
     }
     __syncthreads();
 
@@ -198,12 +247,12 @@ __device__ __forceinline__ void fft_line_mfma(float2 (&x)[16], float* __restrict
         __syncthreads();
     }
 
-    // LDS -> registers, undo the 1/16 per MFMA pass
-    constexpr float undo = (float)(1 << (4 * NMF));
+    // LDS -> registers, undo the 1/16 per MFMA pass and the line's scale
+    const int undo = ex + 4 * NMF;
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
         const int e = sub * LL + mf_pad(t + m * T);
-        x[m] = make_float2(re[e] * undo, im[e] * undo);
+        x[m] = make_float2(ldexpf(re[e], undo), ldexpf(im[e], undo));
     }
     __syncthreads();                              // LDS free for the caller's next use
     if constexpr (G::NP > NMF) {

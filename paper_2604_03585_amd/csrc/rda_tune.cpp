@@ -51,8 +51,13 @@ std::mutex g_mu;
 std::map<Key, int> g_table;
 std::once_flag g_env_once;
 
-bool valid_variant(int kind, int v)
+// Variants a cache entry may select.  Split precisions have the default
+// kernels plus the one-row RCMC kernel only: table twiddles, the split
+// exchange layout and the wide RCMC kernel are FP32 kernels, and the
+// persistent batch grids spill in the split transforms (never faster).
+bool valid_variant(int kind, int prec, int v)
 {
+    if (prec != SAR_FP32) return v == 0 || (kind == sar::TK_RCMC && v == 2);
     switch (kind) {
     case sar::TK_FUSED: return v == 0 || v == 1;
     case sar::TK_FWD:
@@ -112,7 +117,8 @@ bool parse_line(const std::string& line, Entry& e)
     int k = -1;
     for (int i = 0; i < NKIND; ++i)
         if (kind == KIND_NAME[i]) k = i;
-    if (k < 0 || !valid_n((int)n) || prec < SAR_FP32 || prec > SAR_SPLIT_BF16 || !valid_variant(k, (int)v))
+    if (k < 0 || !valid_n((int)n) || prec < SAR_FP32 || prec > SAR_SPLIT_BF16 ||
+        !valid_variant(k, (int)prec, (int)v))
         return false;
     e.key = Key{k, (int)n, (int)prec};
     e.variant = (int)v;
@@ -389,7 +395,7 @@ sar_status sar_autotune(const sar_params* p, const char* cache_path)
             return sar::set_error(SAR_ERR_HIP, "task upload");
         const int groups = sar::line_groups(n, lines);
         std::vector<Candidate> cs;
-        for (int g = 0; g < 4; ++g)
+        for (int g = 0; g < (fp32 ? 4 : 1); ++g)
             for (int tw_tab = 0; tw_tab < (fp32 ? 2 : 1); ++tw_tab) cs.push_back({tw_tab | (g << 2), 0.f});
         sar_status r = time_candidates(
             cs,

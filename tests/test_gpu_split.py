@@ -2,6 +2,11 @@
 hi+lo FP16 or BF16 operands and FP32 accumulation (twiddles, filters, RCMC
 and phases stay in FP32, tables from FP64).
 
+Every line is scaled by a power of two of its own before its values are
+split (its largest component lands in [2^14, 2^15)), so FP16 neither
+overflows nor loses its lo parts to subnormals whatever the input's scale:
+scaling the input by 2^k scales the output by exactly 2^k.
+
 Stated accuracy (checked here against the FP64 oracle):
   split FP16: each operand keeps 22 significand bits (11 + 11), so a line
   FFT stays within 2e-6 and the whole RDA within 1e-5 relative L2, the
@@ -79,3 +84,52 @@ def test_split_rda(prec, name, schedule):
     assert err <= TOL_RDA[prec]
     for t, a, b in zip(sc.targets, rg, ro):
         assert a["peak"] == b["peak"] == (t["m"], t["n"])
+
+
+SCALES = [-20, -12, 12, 16, 20]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("k", SCALES)
+def test_split_line_fft_scaled(prec, k):
+    """Line FFTs of inputs scaled by 2^k: within the same bar as unit-scale
+    inputs against the scaled oracle, and exactly 2^k times the unit-scale
+    output (the per-line exponent absorbs the scale)."""
+    n = 4096
+    rng = np.random.Generator(np.random.PCG64(770 + k))
+    x = rand_c64(rng, (5, n))
+    x[2] *= 1e-3                                    # lines of different scales
+    x[3, 17] = 300.0 + 200.0j                       # a spike over the noise
+    xs = (x * np.float32(2.0 ** k)).astype(np.complex64)
+    with sar.Plan(lfm_cfg(n, 64), precision=prec) as p:
+        out1, outk = empty((5, n)), empty((5, n))
+        sar.sar_fft_lines(p.handle, 0, 0, dev(x), out1, 5)
+        sar.sar_fft_lines(p.handle, 0, 0, dev(xs), outk, 5)
+        g1, gk = host(out1), host(outk)
+    assert np.array_equal(gk, (g1 * np.float32(2.0 ** k)).astype(np.complex64))
+    ref = np.stack([O.fft(r) for r in x.astype(np.complex128)]) * 2.0 ** k
+    for i in range(5):
+        assert rel_l2(gk[i], ref[i]) < TOL_FFT[prec], i
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("k", [-12, 12, 16])
+def test_split_rda_scaled(prec, k):
+    """The c2 scene with its raw data scaled by 2^k (-12: a weak scene whose
+    lo parts would go subnormal; +12, +16: ADC-count-like magnitudes whose
+    range-compressed peaks exceed FP16's 65504 without the per-line scale):
+    within the unit-scale bar against the equally scaled oracle, peaks at the
+    seeded cells, and exactly 2^k times the unit-scale image."""
+    cfg, sc, ref = scene("c2")
+    raw_k = (sc.raw * np.float32(2.0 ** k)).astype(np.complex64)
+    with sar.Plan(cfg, precision=prec) as p:
+        img1 = host(p.execute(dev(sc.raw)))
+        imgk = host(p.execute(dev(raw_k)))
+    assert np.array_equal(imgk, (img1 * np.float32(2.0 ** k)).astype(np.complex64))
+    img = imgk.T
+    err = rel_l2(img, ref * 2.0 ** k)
+    print(f"{prec} c2 x 2^{k}: rel L2 {err:.3e}")
+    assert err <= TOL_RDA[prec]
+    for t in sc.targets:
+        sub = np.abs(img[t["m"] - 8:t["m"] + 9, t["n"] - 8:t["n"] + 9])
+        assert np.unravel_index(int(np.argmax(sub)), sub.shape) == (8, 8)

@@ -19,6 +19,10 @@ CACHE = """\
 {"arch":"gfx950","kind":"nonsense","n":256,"prec":0,"variant":1}
 {"arch":"gfx950","kind":"inv","n":1024,"prec":0,"variant":3}
 {"arch":"gfx950","kind":"fwd","n":1024,"prec":0,"variant":4}
+{"arch":"gfx950","kind":"rcmc","n":2048,"prec":1,"variant":2}
+{"arch":"gfx950","kind":"rcmc","n":1024,"prec":2,"variant":4}
+{"arch":"gfx950","kind":"batch_fused","n":1024,"prec":1,"variant":4}
+{"arch":"gfx950","kind":"fused","n":1024,"prec":2,"variant":1}
 not json at all
 {"arch":"gfx950","kind":"fwd","n":256,"prec":0}
 """
@@ -55,6 +59,11 @@ def test_invalid_lines_are_ignored(cache):
     assert v(_lib.TUNE_FWD, 256, 0) == 0             # no variant field
     assert v(_lib.TUNE_INV, 1024, 0) == 3            # split layout + table twiddles
     assert v(_lib.TUNE_FWD, 1024, 0) == 0            # bit 2 is not a line-kernel variant
+    # split precisions: default kernels and the one-row RCMC kernel only
+    assert v(_lib.TUNE_RCMC, 2048, 1) == 2
+    assert v(_lib.TUNE_RCMC, 1024, 2) == 0           # the wide RCMC kernel is FP32 only
+    assert v(_lib.TUNE_BATCH_FUSED, 1024, 1) == 0    # no persistent split grids
+    assert v(_lib.TUNE_FUSED, 1024, 2) == 0          # table twiddles are FP32 only
 
 
 def test_other_arch_and_clear(cache):
