@@ -167,6 +167,27 @@ sar_status sar_azimuth_compress(sar_plan_t plan, const void* in_dev, void* out_d
 sar_status sar_rda_execute(sar_plan_t plan, const void* raw_dev, void* img_dev,
                            void* work_dev, void* stream);
 
+/* Bytes of the library's static workspace (one per GPU, held from the first
+ * plan on that GPU until the process ends): 128 MiB, the FP32 workspace of
+ * a 4096 x 4096 scene (the paper's scene size). */
+#define SAR_NOALLOC_WORKSPACE_BYTES ((size_t)128 << 20)
+
+/* sar_rda_execute for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The same kernels as sar_rda_execute, with the workspace taken from a
+ * static device array of SAR_NOALLOC_WORKSPACE_BYTES instead of a caller's
+ * buffer; it calls no hipMalloc, hipFree or other allocating routine (the
+ * array's device address is looked up once per GPU by sar_plan).  The caller
+ * passes raw_dev and img_dev as for sar_rda_execute (disjoint).  A plan whose
+ * sar_workspace_bytes exceed SAR_NOALLOC_WORKSPACE_BYTES gets
+ * SAR_ERR_BAD_SIZE; SAR_ERR_HIP if the static array is unavailable on the
+ * plan's device.  Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (other streams, other threads) race on it and
+ * must be serialised by the caller.  Nothing in the array needs to start at
+ * zero (every step writes what the next one reads). */
+sar_status sar_rda_execute_noalloc(sar_plan_t plan, const void* raw_dev, void* img_dev,
+                                   void* stream);
+
 /* ---- individual steps, for step-by-step testing and the unfused path ---- */
 
 /* Forward (inverse = 0) or inverse (inverse = 1, including 1/N) FFT of

@@ -98,6 +98,7 @@ _sar_range_compress = _fn("sar_range_compress", [_vp, _vp, _vp, _vp])
 _sar_corner_turn = _fn("sar_corner_turn", [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp])
 _sar_azimuth_compress = _fn("sar_azimuth_compress", [_vp, _vp, _vp, _vp, _vp])
 _sar_rda_execute = _fn("sar_rda_execute", [_vp, _vp, _vp, _vp, _vp])
+_sar_rda_execute_noalloc = _fn("sar_rda_execute_noalloc", [_vp, _vp, _vp, _vp])
 _sar_fft_lines = _fn("sar_fft_lines", [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
                                        ctypes.c_int32, _vp])
 _sar_azimuth_fft = _fn("sar_azimuth_fft", [_vp, _vp, _vp, _vp])
@@ -222,6 +223,15 @@ def sar_azimuth_compress(plan, in_dev, out_dev, work_dev=None, stream=None):
 def sar_rda_execute(plan, raw_dev, img_dev, work_dev, stream=None):
     _check(_sar_rda_execute(plan, _ptr(raw_dev), _ptr(img_dev), _ptr(work_dev),
                             _stream(stream)), "sar_rda_execute")
+
+
+def sar_rda_execute_noalloc(plan, raw_dev, img_dev, stream=None):
+    _check(_sar_rda_execute_noalloc(plan, _ptr(raw_dev), _ptr(img_dev), _stream(stream)),
+           "sar_rda_execute_noalloc")
+
+
+# sar_rda_execute_noalloc's static workspace (bytes per GPU)
+SAR_NOALLOC_WORKSPACE_BYTES = 128 << 20
 
 
 def sar_fft_lines(plan, axis: int, inverse: int, in_dev, out_dev, lines: int, stream=None):

@@ -20,6 +20,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -65,6 +66,37 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb)
 }
 
 bool misaligned(const void* p) { return ((uintptr_t)p & 15u) != 0; }
+
+// Workspace of sar_rda_execute_noalloc: one array per GPU, held by the loaded
+// code object for the life of the process.  `scratch` names the host-side
+// stand-in of the array; kernels get its device address, which
+// hipGetSymbolAddress returns per device (each device has its own copy).
+// The lookup runs at set-up (sar_plan, with the plan's device current) so the
+// entry point itself calls nothing but the kernels' launches.
+static __device__ __align__(256) unsigned char scratch[SAR_NOALLOC_WORKSPACE_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+hipError_t g_scratch_err[MAX_DEVICES] = {};
+
+// Once per device (the device must be current): look up and keep the
+// device address of `scratch`.  A failure is kept for the entry point to
+// report; plans themselves do not depend on it.
+void setup_noalloc_scratch(int device)
+{
+    if (device < 0 || device >= MAX_DEVICES) return;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_ptr[device] || g_scratch_err[device] != hipSuccess) return;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        g_scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+        (void)hipGetLastError();          // do not leave the error for the caller's next call
+        return;
+    }
+    g_scratch_ptr[device] = ptr;
+}
 
 }  // namespace
 
@@ -401,6 +433,7 @@ sar_status sar_plan(const sar_params* p, void* stream, sar_plan_t* out)
             return cleanup_fail(hip_fail(e, "RCMC weight table generator"));
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup_fail(hip_fail(e, "plan synchronisation"));
+    setup_noalloc_scratch(P->device);
     *out = P;
     return SAR_OK;
 }
@@ -490,6 +523,30 @@ sar_status sar_rda_execute(sar_plan_t P, const void* raw, void* img, void* work,
         if ((st = step_turn(C, C == img ? work : img, Nr, Na, s))) return st;
     }
     return SAR_OK;
+}
+
+sar_status sar_rda_execute_noalloc(sar_plan_t P, const void* raw, void* img, void* stream)
+{
+    g_err.clear();
+    sar_status st;
+    if ((st = check_plan(P))) return st;
+    const size_t need = sar_workspace_bytes(P);
+    if (need > SAR_NOALLOC_WORKSPACE_BYTES)
+        return fail(SAR_ERR_BAD_SIZE,
+                    "sar_rda_execute_noalloc: the plan needs %zu workspace bytes, the library's "
+                    "static workspace holds %zu (use sar_rda_execute with a workspace)",
+                    need, (size_t)SAR_NOALLOC_WORKSPACE_BYTES);
+    void* ptr = nullptr;
+    hipError_t e = hipSuccess;
+    if (P->device >= 0 && P->device < MAX_DEVICES) {
+        std::lock_guard<std::mutex> g(g_scratch_mu);
+        ptr = g_scratch_ptr[P->device];
+        e = g_scratch_err[P->device];
+    }
+    if (!ptr)
+        return fail(SAR_ERR_HIP, "sar_rda_execute_noalloc: no static workspace on device %d (%s)",
+                    P->device, e != hipSuccess ? hipGetErrorString(e) : "set-up did not run");
+    return sar_rda_execute(P, raw, img, ptr, stream);
 }
 
 sar_status sar_fft_lines(sar_plan_t P, int32_t axis, int32_t inverse, const void* in, void* out,

@@ -115,3 +115,18 @@ def test_no_cpu_fallback_in_product_path():
             if f.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"(import|from)\s+oracle|liboracle|orc_", text), f
+
+
+def test_noalloc_workspace_size_matches_header():
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "include", "sar_rda.h")).read()
+    m = re.search(r"#define SAR_NOALLOC_WORKSPACE_BYTES \(\(size_t\)(\d+) << (\d+)\)", hdr)
+    assert m and int(m.group(1)) << int(m.group(2)) == _lib.SAR_NOALLOC_WORKSPACE_BYTES
+
+
+def test_noalloc_rejects_null_plan():
+    with pytest.raises(sar.SarError) as e:
+        sar.sar_rda_execute_noalloc(None, 16, 16, 0)
+    assert e.value.status == _lib.SAR_ERR_NULL
