@@ -12,10 +12,16 @@ first runs its work for --settle-ms of wall time (default 100 ms, untimed)
 so that the GPU clocks have left their idle state, then W warm-up steps,
 then the K timed steps.
 
+The timed steps rotate over three buffer sets (raw scene, workspace,
+image; 3 x 384 MiB against the 256 MiB MALL), so that every step reads its
+raw scene from HBM as a stream of scenes would; one buffer set reused step
+after step and a step after a 512 MiB MALL flush are reported beside it.
+
 Besides the headline it measures, each on the same GPU:
-  kernels_ms    each kernel of the fused pipeline, timed inside the pipeline
-                with HIP events between the launches of a step on the stream
-                they run on (the slowest kernel carries the roofline figure);
+  kernels_ms    each kernel of the fused pipeline inside the pipeline (same
+                rotating buffers and stream, launched back to back), from HIP
+                events that the kernel's own dispatch records at its start
+                and end (the slowest kernel carries the roofline figure);
   hbm_copy_gbs  a plain device copy of one 128 MiB scene buffer (read + write
                 bytes per second): the achievable rate for a pass;
   unfused       the 3-dispatch comparator;
@@ -174,20 +180,40 @@ class Timer:
         return e0.elapsed_time(e1) / reps, wall / reps * 1e3
 
 
+N_SETS = 3   # buffer sets the headline rotates through (3 x 384 MiB >> the 256 MiB MALL)
+
+
 def headline(args, torch, sar, cfg, raw, dev):
     Na, Nr = cfg["Na"], cfg["Nr"]
     px = Na * Nr
-    img = torch.empty((Nr, Na), dtype=torch.complex64, device=dev)
-    work = torch.empty((Na, Nr), dtype=torch.complex64, device=dev)
+    # Step i works on buffer set i mod 3 (raw, work, img; the same scene in
+    # every raw): a set was last touched two steps (768 MiB of traffic)
+    # earlier, so each step reads its raw scene from HBM, as a stream of
+    # different scenes would, not from the 256 MiB MALL.
+    raws = [raw] + [raw.clone() for _ in range(N_SETS - 1)]
+    imgs = [torch.empty((Nr, Na), dtype=torch.complex64, device=dev) for _ in range(N_SETS)]
+    works = [torch.empty((Na, Nr), dtype=torch.complex64, device=dev) for _ in range(N_SETS)]
     stream = torch.cuda.current_stream()
     timed = Timer(torch, stream, args.settle_ms)
     plan = sar.Plan(cfg, schedule="fused")
     h = plan.handle
+    it = [0]
 
-    # ---- the timed region: K whole RDA steps ----
-    ms_event, ms_wall = timed(lambda: sar.sar_rda_execute(h, raw, img, work, stream),
-                              args.steps, args.warmup)
-    images = {"fp32": img.cpu().numpy()}
+    def step():
+        i = it[0] % N_SETS
+        it[0] += 1
+        sar.sar_rda_execute(h, raws[i], imgs[i], works[i], stream)
+
+    # ---- the timed region: K whole RDA steps over rotating buffer sets ----
+    ms_event, ms_wall = timed(step, args.steps, args.warmup)
+    torch.cuda.synchronize()
+    images = {"fp32": imgs[(it[0] - 1) % N_SETS].cpu().numpy()}
+    img, work = imgs[0], works[0]
+
+    # ---- context: one buffer set, step after step (the raw scene and the
+    # previous step's buffers partly stay in the MALL) ----
+    ms_warm, _ = Timer(torch, stream, 30.0)(lambda: sar.sar_rda_execute(h, raw, img, work, stream),
+                                            20, 2)
 
     # ---- cold MALL: 512 MiB written between steps evicts the 256 MiB
     # last-level cache, so every step starts from HBM ----
@@ -205,29 +231,35 @@ def headline(args, torch, sar, cfg, raw, dev):
     ms_cold = sorted(a.elapsed_time(b) for a, b in cold)[len(cold) // 2] if cold else None
     del scratch
 
-    # ---- per-kernel durations inside the pipeline (events between the four
-    # launches of each step: the kernels of sar_rda_execute in the same order,
-    # on the same buffers and stream) ----
-    A, B = work, img
+    # ---- per-kernel durations inside the pipeline: the kernels of
+    # sar_rda_execute in the same order, over the same rotating buffer sets,
+    # on the same stream, launched back to back; each kernel's own start and
+    # end are recorded by its dispatch (sar_time_next_launch), so the
+    # durations are those a profiler's kernel trace reports ----
     names = ["range_fused", "corner_turn", "azimuth_fft", "rcmc_azimuth"]
-    calls = [lambda: sar.sar_range_compress(h, raw, A, stream),
-             lambda: sar.sar_corner_turn(h, A, B, Na, Nr, stream),
-             lambda: sar.sar_azimuth_fft(h, B, A, stream),
-             lambda: sar.sar_rcmc_azimuth(h, A, B, stream)]
+
+    def calls(i):
+        A, B, R = works[i], imgs[i], raws[i]
+        return [lambda: sar.sar_range_compress(h, R, A, stream),
+                lambda: sar.sar_corner_turn(h, A, B, Na, Nr, stream),
+                lambda: sar.sar_azimuth_fft(h, B, A, stream),
+                lambda: sar.sar_rcmc_azimuth(h, A, B, stream)]
     reps = args.kernel_reps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(reps)]
-    for _ in range(2):
-        for c in calls:
-            c()
-    torch.cuda.synchronize()
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(4)] for _ in range(reps)]
+    for row in ev:                         # create the events before the timed launches
+        for a, b in row:
+            a.record(stream)
+            b.record(stream)
+    timed(step, 2, 2)                      # clocks settled again, queue drained
     for r in range(reps):
-        ev[r][0].record(stream)
-        for i, c in enumerate(calls):
+        for i, c in enumerate(calls(r % N_SETS)):
+            sar.sar_time_next_launch(*ev[r][i])
             c()
-            ev[r][i + 1].record(stream)
     torch.cuda.synchronize()
-    kern = {n: sum(ev[r][i].elapsed_time(ev[r][i + 1]) for r in range(reps)) / reps
+    kern = {n: sum(ev[r][i][0].elapsed_time(ev[r][i][1]) for r in range(reps)) / reps
             for i, n in enumerate(names)}
+    del raws, imgs[1:], works[1:]
 
     # ---- achievable HBM rate: a plain device copy of one scene buffer
     # (the runtime's copy kernel), same size and stream as one pass ----
@@ -262,7 +294,7 @@ def headline(args, torch, sar, cfg, raw, dev):
     torch.cuda.synchronize()
     plan.close()
     uplan.close()
-    return ms_event, ms_wall, ms_cold, kern, copy_gbs, ms_unfused, split, images
+    return ms_event, ms_wall, ms_warm, ms_cold, kern, copy_gbs, ms_unfused, split, images
 
 
 def fft_leg(torch, sar, dev):
@@ -427,6 +459,59 @@ def serve_leg(args, torch, sar, dev):
     return out
 
 
+def _median_time(fn, runs):
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        out = fn()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2], out
+
+
+def cpu_baseline_leg(sc2, cfg2):
+    """The FP64 oracle as it stands, on the host cores (compute only; scene
+    generation excluded): the 4096^2 headline scene on all threads (median of
+    3, the reported value) and on one thread (one run: about 15 s), the 256^2
+    LFM scene on all threads and on one (median of 3), and four
+    representative scenes of the 64-scene batch (the quartile sizes) on all
+    threads, once each.  About 25-30 s of CPU work in total."""
+    from oracle import oracle as O
+    from sarsim import batch_configs, config, simulate
+    threads = O.num_threads()
+    px2 = cfg2["Na"] * cfg2["Nr"]
+    legs = {}
+    t, ref = _median_time(lambda: O.rda(sc2.raw, cfg2), 3)
+    legs["c2_all_threads"] = {"s": round(t, 3), "mpx_s": round(px2 / t / 1e6, 2), "runs": 3}
+    cfg1 = config("c1")
+    sc1 = simulate(cfg1)
+    px1 = cfg1["Na"] * cfg1["Nr"]
+    t1, _ = _median_time(lambda: O.rda(sc1.raw, cfg1), 3)
+    legs["c1_all_threads"] = {"s": round(t1, 4), "mpx_s": round(px1 / t1 / 1e6, 2), "runs": 3}
+    cfgs4 = sorted(batch_configs(), key=lambda c: c["Na"] * c["Nr"])
+    picks = [cfgs4[int(q * (len(cfgs4) - 1))] for q in (0.25, 0.5, 0.75, 0.9)]
+    c4 = []
+    for c in picks:
+        s4 = simulate(c)
+        tt, _ = _median_time(lambda: O.rda(s4.raw, c), 1)
+        c4.append({"Na": c["Na"], "Nr": c["Nr"], "s": round(tt, 3),
+                   "mpx_s": round(c["Na"] * c["Nr"] / tt / 1e6, 2)})
+    legs["c4_scenes_all_threads"] = c4
+    O.set_threads(1)
+    try:
+        t1s, _ = _median_time(lambda: O.rda(sc1.raw, cfg1), 3)
+        t2s, _ = _median_time(lambda: O.rda(sc2.raw, cfg2), 1)
+    finally:
+        O.set_threads(threads)
+    legs["c1_one_thread"] = {"s": round(t1s, 4), "mpx_s": round(px1 / t1s / 1e6, 2), "runs": 3}
+    legs["c2_one_thread"] = {"s": round(t2s, 3), "mpx_s": round(px2 / t2s / 1e6, 3), "runs": 1}
+    return {"value": round(px2 / t / 1e6, 2), "unit": "Mpixel/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "the 4096x4096 headline scene, median of 3 runs on all threads (FP64 "
+                      f"oracle, compute only, {t:.2f} s each); legs: one thread, the 256^2 "
+                      "scene, four batch scenes",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "legs": legs}, ref
+
+
 def accuracy(images, sc, ref, cfg):
     """Per precision: relative L2 against the oracle image and the largest
     PSLR / ISLR / SNR differences over the targets; plus the per-target
@@ -481,7 +566,7 @@ def main():
     px = Na * Nr
     raw = torch.from_numpy(sc.raw).to(dev)
 
-    ms_event, ms_wall, ms_cold, kern, copy_gbs, ms_unfused, split, images = headline(
+    ms_event, ms_wall, ms_warm, ms_cold, kern, copy_gbs, ms_unfused, split, images = headline(
         args, torch, sar, cfg, raw, dev)
     log(f"headline: {ms_wall:.4f} ms/step, kernels {kern}, copy {copy_gbs:.0f} GB/s")
     ms_per_step = ms_wall
@@ -528,7 +613,9 @@ def main():
                    "range_tbp": cfg["range_tbp"], "exposure": cfg["exposure"],
                    "schedule": "fused", "parallelism": "none (1 GPU)"},
         "clock_settle_ms": args.settle_ms,
+        "buffer_sets": N_SETS,
         "ms_per_step_event": round(ms_event, 4),
+        "ms_per_step_one_buffer_set": round(ms_warm, 4),
         "ms_per_step_cold_mall": round(ms_cold, 4) if ms_cold is not None else None,
         "design_bytes_per_px": 64,
         "hbm_frac_design": round(design_fused / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -565,16 +652,7 @@ def main():
         out["p99_scene_latency_ms"] = out["serve"]["fp32_64GiB"]["p99_ms"]
 
     if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        threads = O.num_threads()
-        t0 = time.perf_counter()
-        ref = O.rda(sc.raw, cfg)
-        t = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(px / t / 1e6, 2), "unit": "Mpixel/s",
-                               "cores": threads, "kind": "oracle",
-                               "sample": "the full 4096x4096 headline scene once (FP64 "
-                                         f"oracle, compute only, {t:.2f} s)",
-                               "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+        out["cpu_baseline"], ref = cpu_baseline_leg(sc, cfg)
         out["accuracy_vs_oracle"] = accuracy(images, sc, ref, cfg)
     print(json.dumps(out))
 

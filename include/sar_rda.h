@@ -188,6 +188,20 @@ sar_status sar_rda_execute(sar_plan_t plan, const void* raw_dev, void* img_dev,
 sar_status sar_rda_execute_noalloc(sar_plan_t plan, const void* raw_dev, void* img_dev,
                                    void* stream);
 
+/* Measurement (the per-kernel durations the benchmark reports, Sec. V.C
+ * Table III's per-step breakdown): the next kernel launched by the library on
+ * the calling thread records start_event when that kernel starts and
+ * stop_event when it ends.  The timestamps come from the kernel's own
+ * dispatch (hipExtLaunchKernel), so their interval is the kernel's duration
+ * as a profiler's kernel trace reports it, without the launch gaps that
+ * events recorded between launches include.  Both are hipEvent_t the caller
+ * created with timing enabled and keeps alive until they have completed;
+ * NULL, NULL disarms.  One event given without the other: SAR_ERR_NULL.
+ * Each step entry point that launches a single kernel (sar_range_compress
+ * and sar_azimuth_fft of a fused FP32 plan, sar_corner_turn,
+ * sar_rcmc_azimuth) is thereby timed whole. */
+sar_status sar_time_next_launch(void* start_event, void* stop_event);
+
 /* ---- individual steps, for step-by-step testing and the unfused path ---- */
 
 /* Forward (inverse = 0) or inverse (inverse = 1, including 1/N) FFT of

@@ -99,6 +99,7 @@ _sar_corner_turn = _fn("sar_corner_turn", [_vp, _vp, _vp, ctypes.c_int32, ctypes
 _sar_azimuth_compress = _fn("sar_azimuth_compress", [_vp, _vp, _vp, _vp, _vp])
 _sar_rda_execute = _fn("sar_rda_execute", [_vp, _vp, _vp, _vp, _vp])
 _sar_rda_execute_noalloc = _fn("sar_rda_execute_noalloc", [_vp, _vp, _vp, _vp])
+_sar_time_next_launch = _fn("sar_time_next_launch", [_vp, _vp])
 _sar_fft_lines = _fn("sar_fft_lines", [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
                                        ctypes.c_int32, _vp])
 _sar_azimuth_fft = _fn("sar_azimuth_fft", [_vp, _vp, _vp, _vp])
@@ -223,6 +224,22 @@ def sar_azimuth_compress(plan, in_dev, out_dev, work_dev=None, stream=None):
 def sar_rda_execute(plan, raw_dev, img_dev, work_dev, stream=None):
     _check(_sar_rda_execute(plan, _ptr(raw_dev), _ptr(img_dev), _ptr(work_dev),
                             _stream(stream)), "sar_rda_execute")
+
+
+def sar_time_next_launch(start_event, stop_event):
+    """Arm two events (torch.cuda.Event with timing, or raw hipEvent_t handles;
+    None, None disarms) for the next kernel launch on this thread.  A torch
+    event whose handle does not exist yet is created by recording it once."""
+    def handle(e):
+        if e is None:
+            return None
+        if hasattr(e, "cuda_event"):
+            if not e.cuda_event:
+                import torch
+                e.record(torch.cuda.current_stream())
+            return int(e.cuda_event)
+        return int(e)
+    _check(_sar_time_next_launch(handle(start_event), handle(stop_event)), "sar_time_next_launch")
 
 
 def sar_rda_execute_noalloc(plan, raw_dev, img_dev, stream=None):

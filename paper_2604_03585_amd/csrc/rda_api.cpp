@@ -100,7 +100,20 @@ void setup_noalloc_scratch(int device)
 
 }  // namespace
 
+namespace {
+thread_local hipEvent_t g_time_start = nullptr, g_time_stop = nullptr;
+}  // namespace
+
 namespace sar {
+bool take_launch_events(hipEvent_t& start, hipEvent_t& stop)
+{
+    if (!g_time_start) return false;
+    start = g_time_start;
+    stop = g_time_stop;
+    g_time_start = g_time_stop = nullptr;
+    return true;
+}
+
 sar_status set_error(sar_status st, const char* fmt, ...)
 {
     char buf[512];
@@ -522,6 +535,16 @@ sar_status sar_rda_execute(sar_plan_t P, const void* raw, void* img, void* work,
     if (back) {
         if ((st = step_turn(C, C == img ? work : img, Nr, Na, s))) return st;
     }
+    return SAR_OK;
+}
+
+sar_status sar_time_next_launch(void* start_event, void* stop_event)
+{
+    g_err.clear();
+    if (!start_event != !stop_event)
+        return fail(SAR_ERR_NULL, "sar_time_next_launch: give both events or neither");
+    g_time_start = (hipEvent_t)start_event;
+    g_time_stop = (hipEvent_t)stop_event;
     return SAR_OK;
 }
 

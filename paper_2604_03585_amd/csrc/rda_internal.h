@@ -16,6 +16,11 @@ namespace sar {
 sar_status set_error(sar_status st, const char* fmt, ...);
 void clear_error();
 
+// The events sar_time_next_launch armed on this thread, if any: taken (and
+// disarmed) by the next kernel launch, which records them at its start and
+// end.
+bool take_launch_events(hipEvent_t& start, hipEvent_t& stop);
+
 enum class LineOp { Fused, Forward, Inverse, RcmcAz };
 
 // One scene's share of a batched line launch: `lines` lines of `in` -> `out`

@@ -20,6 +20,7 @@
 //                    + IFFT per output range line, fused (Sec. IV.A steps 3-4).
 //   k_rcmc_interp,   the same two steps as separate dispatches for the
 //   k_az_phase       unfused comparator.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -28,6 +29,20 @@
 #include "fft_line.hpp"
 #include "mfma_fft.hpp"
 #include "rda_internal.h"
+
+// Every kernel launch of the library.  When sar_time_next_launch has armed
+// two events on this thread, the launch records them at the kernel's start
+// and end (hipExtLaunchKernel takes the dispatch's own timestamps, so the
+// interval is the kernel's duration alone).
+#define SAR_LAUNCH(kernel, grid, block, lds, stream, ...)                                  \
+    do {                                                                                   \
+        hipEvent_t sar_e0_, sar_e1_;                                                       \
+        if (sar::take_launch_events(sar_e0_, sar_e1_))                                     \
+            hipExtLaunchKernelGGL(kernel, grid, block, lds, stream, sar_e0_, sar_e1_, 0,   \
+                                  __VA_ARGS__);                                            \
+        else                                                                               \
+            hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);             \
+    } while (0)
 
 namespace sar {
 
@@ -1277,19 +1292,19 @@ static hipError_t launch_k_line(const float2* in, float2* out, int lines, const 
     if constexpr (PREC == PREC_FP32 && KIND != LK_FUSED) {
         if (variant & 2) {
             if (variant & 1)
-                hipLaunchKernelGGL((k_line<N, KIND, PREC, false, true>), dim3(groups), dim3(L::BLOCK),
+                SAR_LAUNCH((k_line<N, KIND, PREC, false, true>), dim3(groups), dim3(L::BLOCK),
                                    L::LDS_BYTES, s, in, out, lines, H, tw, scale);
             else
-                hipLaunchKernelGGL((k_line<N, KIND, PREC, true, true>), dim3(groups), dim3(L::BLOCK),
+                SAR_LAUNCH((k_line<N, KIND, PREC, true, true>), dim3(groups), dim3(L::BLOCK),
                                    L::LDS_BYTES, s, in, out, lines, H, tw, scale);
             return hipGetLastError();
         }
     }
     if (PREC == PREC_FP32 && (variant & 1))
-        hipLaunchKernelGGL((k_line<N, KIND, PREC, false>), dim3(groups), dim3(L::BLOCK),
+        SAR_LAUNCH((k_line<N, KIND, PREC, false>), dim3(groups), dim3(L::BLOCK),
                            L::LDS_BYTES, s, in, out, lines, H, tw, scale);
     else
-        hipLaunchKernelGGL((k_line<N, KIND, PREC, true>), dim3(groups), dim3(L::BLOCK),
+        SAR_LAUNCH((k_line<N, KIND, PREC, true>), dim3(groups), dim3(L::BLOCK),
                            L::LDS_BYTES, s, in, out, lines, H, tw, scale);
     return hipGetLastError();
 }
@@ -1326,20 +1341,20 @@ static hipError_t launch_line_n(LineOp op, const float2* in, float2* out, int li
                                                             hipFuncAttributeMaxDynamicSharedMemorySize,
                                                             lds2);
                 if (wa != hipSuccess) return wa;
-                hipLaunchKernelGGL((k_rcmc_az2w<N>), dim3(lines / 2), dim3(2 * LineGeom<N>::T), lds2,
+                SAR_LAUNCH((k_rcmc_az2w<N>), dim3(lines / 2), dim3(2 * LineGeom<N>::T), lds2,
                                    s, in, out, *ra, tw);
                 return hipGetLastError();
             }
         }
         if (two_rows) {
             const int g2 = (lines / 2 + L::LPW - 1) / L::LPW;
-            hipLaunchKernelGGL((k_rcmc_az2<N, PREC>), dim3(g2), dim3(L::BLOCK), L::LDS_BYTES, s, in,
+            SAR_LAUNCH((k_rcmc_az2<N, PREC>), dim3(g2), dim3(L::BLOCK), L::LDS_BYTES, s, in,
                                out, *ra, tw);
         } else if (taps == 8)
-            hipLaunchKernelGGL((k_rcmc_az<N, 8, PREC>), dim3(groups), dim3(L::BLOCK), L::LDS_BYTES,
+            SAR_LAUNCH((k_rcmc_az<N, 8, PREC>), dim3(groups), dim3(L::BLOCK), L::LDS_BYTES,
                                s, in, out, *ra, tw);
         else
-            hipLaunchKernelGGL((k_rcmc_az<N, 0, PREC>), dim3(groups), dim3(L::BLOCK), L::LDS_BYTES,
+            SAR_LAUNCH((k_rcmc_az<N, 0, PREC>), dim3(groups), dim3(L::BLOCK), L::LDS_BYTES,
                                s, in, out, *ra, tw);
         return hipGetLastError();
     }
@@ -1354,15 +1369,15 @@ static void launch_line_batch_k(int kind, int grid, const LineTask* tasks, int n
     using L = LineLaunch<N>;
     switch (kind) {
     case LK_FUSED:
-        hipLaunchKernelGGL((k_line_batch<N, LK_FUSED, PREC, TWP, PERSIST>), dim3(grid),
+        SAR_LAUNCH((k_line_batch<N, LK_FUSED, PREC, TWP, PERSIST>), dim3(grid),
                            dim3(L::BLOCK), L::LDS_BYTES, s, tasks, ntasks, total_groups, scale);
         break;
     case LK_FWD:
-        hipLaunchKernelGGL((k_line_batch<N, LK_FWD, PREC, TWP, PERSIST>), dim3(grid),
+        SAR_LAUNCH((k_line_batch<N, LK_FWD, PREC, TWP, PERSIST>), dim3(grid),
                            dim3(L::BLOCK), L::LDS_BYTES, s, tasks, ntasks, total_groups, scale);
         break;
     default:
-        hipLaunchKernelGGL((k_line_batch<N, LK_INV, PREC, TWP, PERSIST>), dim3(grid),
+        SAR_LAUNCH((k_line_batch<N, LK_INV, PREC, TWP, PERSIST>), dim3(grid),
                            dim3(L::BLOCK), L::LDS_BYTES, s, tasks, ntasks, total_groups, scale);
         break;
     }
@@ -1490,7 +1505,7 @@ static hipError_t launch_hs_n(const void* in, void* out, int lines, const void* 
     if (attr != hipSuccess) return attr;
     const int groups = (lines + L::LPW - 1) / L::LPW;
     if (groups == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_line_hs<N, KIND, IN_H, OUT_H>), dim3(groups), dim3(L::BLOCK),
+    SAR_LAUNCH((k_line_hs<N, KIND, IN_H, OUT_H>), dim3(groups), dim3(L::BLOCK),
                        L::LDS_BYTES, s, in, out, lines, (const float2*)H, (const float2*)tw, ex_in,
                        ex_out);
     return hipGetLastError();
@@ -1542,7 +1557,7 @@ static hipError_t launch_rcmc_half_n(const void* A, const int* ex, void* out, co
     ra.row_exp = ex;
     const int g2 = (ra.nr / 2 + L::LPW - 1) / L::LPW;
     if (g2 == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_rcmc_az2<N, PREC_FP32, true>), dim3(g2), dim3(L::BLOCK), L::LDS_BYTES, s,
+    SAR_LAUNCH((k_rcmc_az2<N, PREC_FP32, true>), dim3(g2), dim3(L::BLOCK), L::LDS_BYTES, s,
                        A, (float2*)out, ra, (const float2*)tw);
     return hipGetLastError();
 }
@@ -1620,7 +1635,7 @@ hipError_t launch_corner_turn_batch(const void* tasks, int ntasks, int total_til
 {
     if (total_tiles == 0) return hipSuccess;
     const int grid = total_tiles < 256 * 16 ? total_tiles : 256 * 16;
-    hipLaunchKernelGGL(k_corner_turn_batch, dim3(grid), dim3(256), 0, s, (const TurnTask*)tasks,
+    SAR_LAUNCH(k_corner_turn_batch, dim3(grid), dim3(256), 0, s, (const TurnTask*)tasks,
                        ntasks, total_tiles);
     return hipGetLastError();
 }
@@ -1653,7 +1668,7 @@ int twiddle_table_size(int n)
 hipError_t launch_rowmul(const void* in, void* out, int rows, int n, const void* H, hipStream_t s)
 {
     const long long pairs = (long long)rows * n / 2;
-    hipLaunchKernelGGL(k_rowmul, dim3(grid_for(pairs, 256)), dim3(256), 0, s, (const float4*)in,
+    SAR_LAUNCH(k_rowmul, dim3(grid_for(pairs, 256)), dim3(256), 0, s, (const float4*)in,
                        (float4*)out, pairs, n, (const float2*)H);
     return hipGetLastError();
 }
@@ -1664,7 +1679,7 @@ hipError_t launch_corner_turn_b4(const void* in, void* out, int rows, int cols, 
         return hipErrorInvalidValue;
     const long long tiles = (long long)(rows / TT) * (cols / TT);
     if (tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_corner_turn_b4, dim3((unsigned)tiles), dim3(256), 0, s, (const uint2*)in,
+    SAR_LAUNCH(k_corner_turn_b4, dim3((unsigned)tiles), dim3(256), 0, s, (const uint2*)in,
                        (uint2*)out, rows, cols);
     return hipGetLastError();
 }
@@ -1680,11 +1695,11 @@ hipError_t launch_corner_turn(const void* in, void* out, int rows, int cols, hip
         // holds), each taking the same number of tiles (the last round ragged)
         const long long per = (tiles + 1279) / 1280;
         const long long grid = (tiles + per - 1) / per;
-        hipLaunchKernelGGL(k_corner_turn_x2, dim3((unsigned)grid), dim3(256), 0, s,
+        SAR_LAUNCH(k_corner_turn_x2, dim3((unsigned)grid), dim3(256), 0, s,
                            (const float4*)in, (float4*)out, rows, cols, (int)tiles);
     }
     else
-        hipLaunchKernelGGL(k_corner_turn, dim3((unsigned)tiles), dim3(256), 0, s,
+        SAR_LAUNCH(k_corner_turn, dim3((unsigned)tiles), dim3(256), 0, s,
                            (const float2*)in, (float2*)out, rows, cols);
     return hipGetLastError();
 }
@@ -1694,10 +1709,10 @@ hipError_t launch_rcmc_interp(const void* A, void* out, int na, const RcmcHost& 
     const RcmcArgs ra = make_rcmc_args(rh);
     const long long total = (long long)rh.nr * na;
     if (rh.taps == 8)
-        hipLaunchKernelGGL(k_rcmc_interp<8>, dim3(grid_for(total, 256)), dim3(256), 0, s,
+        SAR_LAUNCH(k_rcmc_interp<8>, dim3(grid_for(total, 256)), dim3(256), 0, s,
                            (const float2*)A, (float2*)out, na, ra);
     else
-        hipLaunchKernelGGL(k_rcmc_interp<0>, dim3(grid_for(total, 256)), dim3(256), 0, s,
+        SAR_LAUNCH(k_rcmc_interp<0>, dim3(grid_for(total, 256)), dim3(256), 0, s,
                            (const float2*)A, (float2*)out, na, ra);
     return hipGetLastError();
 }
@@ -1707,7 +1722,7 @@ hipError_t launch_az_phase(const void* in, void* out, int na, const RcmcHost& rh
 {
     const RcmcArgs ra = make_rcmc_args(rh);
     const long long total = (long long)rh.nr * na;
-    hipLaunchKernelGGL(k_az_phase, dim3(grid_for(total, 256)), dim3(256), 0, s, (const float2*)in,
+    SAR_LAUNCH(k_az_phase, dim3(grid_for(total, 256)), dim3(256), 0, s, (const float2*)in,
                        (float2*)out, na, ra, scale);
     return hipGetLastError();
 }
@@ -1716,7 +1731,7 @@ hipError_t launch_gen_twiddles(void* tw, int n, hipStream_t s)
 {
     const int cnt = twiddle_table_size(n);
     if (cnt <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gen_twiddles, dim3((cnt + 255) / 256), dim3(256), 0, s, (float2*)tw, n,
+    SAR_LAUNCH(k_gen_twiddles, dim3((cnt + 255) / 256), dim3(256), 0, s, (float2*)tw, n,
                        line_e(n));
     return hipGetLastError();
 }
@@ -1724,14 +1739,14 @@ hipError_t launch_gen_twiddles(void* tw, int n, hipStream_t s)
 hipError_t launch_gen_chirp_filter(void* H, int n, int len, double K, int sign, double scale,
                                    hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gen_chirp_filter, dim3((n + 255) / 256), dim3(256), 0, s, (float2*)H, n,
+    SAR_LAUNCH(k_gen_chirp_filter, dim3((n + 255) / 256), dim3(256), 0, s, (float2*)H, n,
                        len, K, sign, scale);
     return hipGetLastError();
 }
 
 hipError_t launch_gen_rcmc_table(float* tab, double beta, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gen_rcmc_table, dim3(1), dim3(RCMC_INTERVALS), 0, s, tab, beta);
+    SAR_LAUNCH(k_gen_rcmc_table, dim3(1), dim3(RCMC_INTERVALS), 0, s, tab, beta);
     return hipGetLastError();
 }
 
@@ -1741,7 +1756,7 @@ hipError_t launch_gen_hyper_tables(double* stretch, double* rate, int na, double
                                    hipStream_t s)
 {
     // the same expressions as the kernels' RcmcArgs (x_per_bin, two_over_lam)
-    hipLaunchKernelGGL(k_gen_hyper_tables, dim3((na + 255) / 256), dim3(256), 0, s, stretch, rate,
+    SAR_LAUNCH(k_gen_hyper_tables, dim3((na + 255) / 256), dim3(256), 0, s, stretch, rate,
                        na, lam / (2.0 * v * (double)na), 2.0 / lam);
     return hipGetLastError();
 }

@@ -130,3 +130,10 @@ def test_noalloc_rejects_null_plan():
     with pytest.raises(sar.SarError) as e:
         sar.sar_rda_execute_noalloc(None, 16, 16, 0)
     assert e.value.status == _lib.SAR_ERR_NULL
+
+
+def test_time_next_launch_wants_both_events_or_neither():
+    with pytest.raises(sar.SarError) as e:
+        sar.sar_time_next_launch(16, None)
+    assert e.value.status == _lib.SAR_ERR_NULL
+    sar.sar_time_next_launch(None, None)     # disarm: always fine, no GPU call

@@ -212,3 +212,27 @@ def test_execute_rejects_aliasing(plans):
     assert ei.value.status == sar._lib.SAR_ERR_ALIAS
     with pytest.raises(sar.SarError):
         sar.sar_corner_turn(p.handle, buf[0], buf[0], 256, 256)
+
+
+def test_time_next_launch_brackets_one_kernel():
+    """The armed events record the next launch only: a corner turn of 128 MiB
+    timed by its own dispatch takes between the time of moving its bytes at
+    16 TB/s and 10 ms, and the launch after it leaves the events alone."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(31))
+    x = dev(rand_c64(rng, (4096, 4096)))
+    out = empty((4096, 4096))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s = torch.cuda.current_stream()
+    e0.record(s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    sar.sar_time_next_launch(e0, e1)
+    sar.sar_corner_turn(0, x, out, 4096, 4096)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    assert 2 * 4096 * 4096 * 8 / 16e12 * 1e3 < ms < 10.0, ms
+    sar.sar_corner_turn(0, out, x, 4096, 4096)      # not armed: events unchanged
+    torch.cuda.synchronize()
+    assert e0.elapsed_time(e1) == ms
+    print(f"corner turn 4096^2 by its own dispatch: {ms * 1e3:.1f} us")
