@@ -3,8 +3,10 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                     [--no-split] [--no-batch] [--no-serve]
 
-A step is one whole RDA (range compression, corner turn, azimuth FFT, RCMC +
-azimuth compression) over the 4096 x 4096 complex64 hyperbolic scene
+A step is one whole RDA (range compression, azimuth FFT, RCMC + azimuth
+compression; in the turn-free schedule, whose azimuth kernel reads strips of
+azimuth lines straight from the range output, so no corner turn) over the
+4096 x 4096 complex64 hyperbolic scene
 (512-sample range chirp TBP 200, 1024-pulse aperture with up to 8 cells of
 range migration, 8-tap Kaiser-sinc RCMC, 5 point targets, 20 dB noise),
 with the raw scene resident in HBM.  Prints one JSON line.  Each timed leg
@@ -18,10 +20,13 @@ raw scene from HBM as a stream of scenes would; one buffer set reused step
 after step and a step after a 512 MiB MALL flush are reported beside it.
 
 Besides the headline it measures, each on the same GPU:
-  kernels_ms    each kernel of the fused pipeline inside the pipeline (same
-                rotating buffers and stream, launched back to back), from HIP
+  kernels_ms    each kernel of the headline step (same rotating buffers and
+                stream, launched back to back by sar_rda_execute), from HIP
                 events that the kernel's own dispatch records at its start
                 and end (the slowest kernel carries the roofline figure);
+  fused_turned  the same scene through the fused schedule with its corner
+                turn (64 B/px), with its kernels, and whether its image
+                equals the turn-free one bit for bit;
   hbm_copy_gbs  a plain device copy of one 128 MiB scene buffer (read + write
                 bytes per second): the achievable rate for a pass;
   unfused       the 3-dispatch comparator;
@@ -52,6 +57,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
 PAPER_FUSED_MPX = 4096 * 4096 / 0.37 / 1e6   # Apple M1 fused RDA, Table II
@@ -59,7 +66,7 @@ PAPER_FUSED_MPX = 4096 * 4096 / 0.37 / 1e6   # Apple M1 fused RDA, Table II
 # Algorithmic bytes per pixel of each kernel launch (read + write complex64);
 # filters and per-bin tables are excluded (they stay in L2).
 KERNEL_BYTES_PER_PX = {"range_fused": 16, "corner_turn": 16, "azimuth_fft": 16,
-                       "rcmc_azimuth": 16}
+                       "azimuth_strip_fft": 16, "rcmc_azimuth": 16}
 KERNEL_SOURCES = ["rda_kernels.inl", "fft_line.hpp", "mfma_fft.hpp", "rda_part_fp32.hip"]
 GiB = 1 << 30
 
@@ -180,12 +187,15 @@ class Timer:
         return e0.elapsed_time(e1) / reps, wall / reps * 1e3
 
 
-N_SETS = 3   # buffer sets the headline rotates through (3 x 384 MiB >> the 256 MiB MALL)
+N_SETS = 3   # buffer sets the timed steps rotate through (3 x 384 MiB >> the 256 MiB MALL)
+KERNELS = {   # the kernels sar_rda_execute launches for the 4096^2 hyperbolic scene
+    "turn_free": ["range_fused", "azimuth_strip_fft", "rcmc_azimuth"],
+    "fused": ["range_fused", "corner_turn", "azimuth_fft", "rcmc_azimuth"],
+}
 
 
 def headline(args, torch, sar, cfg, raw, dev):
     Na, Nr = cfg["Na"], cfg["Nr"]
-    px = Na * Nr
     # Step i works on buffer set i mod 3 (raw, work, img; the same scene in
     # every raw): a set was last touched two steps (768 MiB of traffic)
     # earlier, so each step reads its raw scene from HBM, as a stream of
@@ -195,20 +205,55 @@ def headline(args, torch, sar, cfg, raw, dev):
     works = [torch.empty((Na, Nr), dtype=torch.complex64, device=dev) for _ in range(N_SETS)]
     stream = torch.cuda.current_stream()
     timed = Timer(torch, stream, args.settle_ms)
-    plan = sar.Plan(cfg, schedule="fused")
-    h = plan.handle
+    plans = {s: sar.Plan(cfg, schedule=s) for s in ("turn_free", "fused")}
     it = [0]
 
-    def step():
-        i = it[0] % N_SETS
-        it[0] += 1
-        sar.sar_rda_execute(h, raws[i], imgs[i], works[i], stream)
+    def stepper(plan):
+        h = plan.handle
 
-    # ---- the timed region: K whole RDA steps over rotating buffer sets ----
-    ms_event, ms_wall = timed(step, args.steps, args.warmup)
+        def step():
+            i = it[0] % N_SETS
+            it[0] += 1
+            sar.sar_rda_execute(h, raws[i], imgs[i], works[i], stream)
+        return step
+
+    def breakdown(plan, names, reps):
+        """Per-kernel durations of whole steps: the events of every kernel
+        sar_rda_execute launches are recorded by the kernels' own dispatches."""
+        ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in names] for _ in range(reps)]
+        for row in ev:                     # create the events before the timed launches
+            for a, b in row:
+                a.record(stream)
+                b.record(stream)
+        step = stepper(plan)
+        timed(step, 2, 2)                  # clocks settled again, queue drained
+        for r in range(reps):
+            sar.sar_time_next_launches([a for a, _ in ev[r]], [b for _, b in ev[r]])
+            step()
+        torch.cuda.synchronize()
+        return {n: sum(ev[r][i][0].elapsed_time(ev[r][i][1]) for r in range(reps)) / reps
+                for i, n in enumerate(names)}
+
+    # ---- the timed region: K whole RDA steps over rotating buffer sets, in
+    # the turn-free schedule (no corner turn; the fastest, and bit-identical
+    # to the turned one) ----
+    ms_event, ms_wall = timed(stepper(plans["turn_free"]), args.steps, args.warmup)
     torch.cuda.synchronize()
-    images = {"fp32": imgs[(it[0] - 1) % N_SETS].cpu().numpy()}
+    last = (it[0] - 1) % N_SETS
+    images = {"fp32": imgs[last].cpu().numpy()}
+    kern = breakdown(plans["turn_free"], KERNELS["turn_free"], args.kernel_reps)
+
+    # ---- the same scene with the corner turn (fused schedule), timed the
+    # same way; its image must equal the turn-free one bit for bit ----
+    ms_turned, _ = timed(stepper(plans["fused"]), args.steps, args.warmup)
+    torch.cuda.synchronize()
+    same = bool(np.array_equal(imgs[(it[0] - 1) % N_SETS].cpu().numpy().view(np.uint32),
+                               images["fp32"].view(np.uint32)))
+    kern_turned = breakdown(plans["fused"], KERNELS["fused"], args.kernel_reps)
+    turned = {"ms_per_step": ms_turned, "kernels_ms": kern_turned, "image_equal": same}
     img, work = imgs[0], works[0]
+    h = plans["turn_free"].handle
 
     # ---- context: one buffer set, step after step (the raw scene and the
     # previous step's buffers partly stay in the MALL) ----
@@ -229,37 +274,8 @@ def headline(args, torch, sar, cfg, raw, dev):
         cold.append((e0, e1))
     torch.cuda.synchronize()
     ms_cold = sorted(a.elapsed_time(b) for a, b in cold)[len(cold) // 2] if cold else None
-    del scratch
-
-    # ---- per-kernel durations inside the pipeline: the kernels of
-    # sar_rda_execute in the same order, over the same rotating buffer sets,
-    # on the same stream, launched back to back; each kernel's own start and
-    # end are recorded by its dispatch (sar_time_next_launch), so the
-    # durations are those a profiler's kernel trace reports ----
-    names = ["range_fused", "corner_turn", "azimuth_fft", "rcmc_azimuth"]
-
-    def calls(i):
-        A, B, R = works[i], imgs[i], raws[i]
-        return [lambda: sar.sar_range_compress(h, R, A, stream),
-                lambda: sar.sar_corner_turn(h, A, B, Na, Nr, stream),
-                lambda: sar.sar_azimuth_fft(h, B, A, stream),
-                lambda: sar.sar_rcmc_azimuth(h, A, B, stream)]
-    reps = args.kernel_reps
-    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(4)] for _ in range(reps)]
-    for row in ev:                         # create the events before the timed launches
-        for a, b in row:
-            a.record(stream)
-            b.record(stream)
-    timed(step, 2, 2)                      # clocks settled again, queue drained
-    for r in range(reps):
-        for i, c in enumerate(calls(r % N_SETS)):
-            sar.sar_time_next_launch(*ev[r][i])
-            c()
-    torch.cuda.synchronize()
-    kern = {n: sum(ev[r][i][0].elapsed_time(ev[r][i][1]) for r in range(reps)) / reps
-            for i, n in enumerate(names)}
-    del raws, imgs[1:], works[1:]
+    del scratch, raws, imgs[1:], works[1:]
+    plan = plans["turn_free"]
 
     # ---- achievable HBM rate: a plain device copy of one scene buffer
     # (the runtime's copy kernel), same size and stream as one pass ----
@@ -292,9 +308,10 @@ def headline(args, torch, sar, cfg, raw, dev):
             "design_bytes_per_px": 40,
             "hbm_frac_design": round(40 * px / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     torch.cuda.synchronize()
-    plan.close()
+    for p in plans.values():
+        p.close()
     uplan.close()
-    return ms_event, ms_wall, ms_warm, ms_cold, kern, copy_gbs, ms_unfused, split, images
+    return ms_event, ms_wall, ms_warm, ms_cold, kern, turned, copy_gbs, ms_unfused, split, images
 
 
 def fft_leg(torch, sar, dev):
@@ -566,8 +583,8 @@ def main():
     px = Na * Nr
     raw = torch.from_numpy(sc.raw).to(dev)
 
-    ms_event, ms_wall, ms_warm, ms_cold, kern, copy_gbs, ms_unfused, split, images = headline(
-        args, torch, sar, cfg, raw, dev)
+    ms_event, ms_wall, ms_warm, ms_cold, kern, turned, copy_gbs, ms_unfused, split, images = \
+        headline(args, torch, sar, cfg, raw, dev)
     log(f"headline: {ms_wall:.4f} ms/step, kernels {kern}, copy {copy_gbs:.0f} GB/s")
     ms_per_step = ms_wall
     value = px / (ms_per_step * 1e-3) / 1e6
@@ -589,6 +606,7 @@ def main():
                       "lds_conflict_ratio": irec["lds_conflict_ratio"],
                       "source": irec["source"]}
 
+    design_tf = 48 * px           # range 16 + strip az FFT 16 + RCMC/az 16
     design_fused = 64 * px        # range 16 + turn 16 + az FFT 16 + RCMC/az 16
     design_unfused = 128 * px     # range 48 + turn 16 + az FFT 16 + RCMC 16 + xH 16 + IFFT 16
     flops = 2 * Na * 5 * Nr * math.log2(Nr) + 2 * Nr * 5 * Na * math.log2(Na)
@@ -611,16 +629,28 @@ def main():
         "config": {"workload": "4096x4096 c64 hyperbolic RDA, 8-tap RCMC, 5 targets, 20 dB",
                    "Na": Na, "Nr": Nr, "range_len": cfg["range_len"],
                    "range_tbp": cfg["range_tbp"], "exposure": cfg["exposure"],
-                   "schedule": "fused", "parallelism": "none (1 GPU)"},
+                   "schedule": "turn_free (fused kernels, no corner turn)",
+                   "parallelism": "none (1 GPU)"},
         "clock_settle_ms": args.settle_ms,
         "buffer_sets": N_SETS,
         "ms_per_step_event": round(ms_event, 4),
         "ms_per_step_one_buffer_set": round(ms_warm, 4),
         "ms_per_step_cold_mall": round(ms_cold, 4) if ms_cold is not None else None,
-        "design_bytes_per_px": 64,
-        "hbm_frac_design": round(design_fused / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "design_bytes_per_px": 48,
+        "hbm_frac_design": round(design_tf / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        # the step time against the turned path's 64 B/px: 60% of 8 TB/s at
+        # 64 B/px is 224 us per 4096^2 step
+        "hbm_frac_64B_equivalent": round(design_fused / (ms_per_step * 1e-3) / 1e9
+                                         / HBM_PEAK_GBS, 4),
         "fft_gflops": round(flops / (ms_per_step * 1e-3) / 1e9, 1),
         "kernels_ms": {k: round(v, 4) for k, v in kern.items()},
+        "fused_turned": {"ms_per_step": round(turned["ms_per_step"], 4),
+                         "value": round(px / (turned["ms_per_step"] * 1e-3) / 1e6, 1),
+                         "design_bytes_per_px": 64,
+                         "hbm_frac_design": round(design_fused / (turned["ms_per_step"] * 1e-3)
+                                                  / 1e9 / HBM_PEAK_GBS, 4),
+                         "kernels_ms": {k: round(v, 4) for k, v in turned["kernels_ms"].items()},
+                         "image_bit_identical_to_turn_free": turned["image_equal"]},
         "hbm_copy_gbs": round(copy_gbs, 1),
         "unfused": {"ms_per_step": round(ms_unfused, 4),
                     "value": round(px / (ms_unfused * 1e-3) / 1e6, 1),

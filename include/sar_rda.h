@@ -64,7 +64,7 @@ typedef enum {
     SAR_SPLIT_BF16 = 2,
     SAR_FP32_HALF_STORAGE = 3
 } sar_precision;
-typedef enum { SAR_FUSED = 0, SAR_UNFUSED = 1 } sar_schedule;
+typedef enum { SAR_FUSED = 0, SAR_UNFUSED = 1, SAR_TURN_FREE = 2 } sar_schedule;
 
 /*
  * Processing parameters (normalised units: one range cell = 1, one pulse
@@ -103,7 +103,15 @@ typedef enum { SAR_FUSED = 0, SAR_UNFUSED = 1 } sar_schedule;
  *                  complex64, run as SAR_FP32.
  *  schedule        SAR_FUSED (one kernel per line pass) or SAR_UNFUSED
  *                  (separate FFT, multiply and IFFT dispatches, Sec. II.B
- *                  Fig. 1 top) -- the comparator.
+ *                  Fig. 1 top) -- the comparator -- or SAR_TURN_FREE: the
+ *                  fused kernels without the corner turn (Sec. VI, future
+ *                  work on the transposes that dominate the azimuth steps):
+ *                  sar_rda_execute's azimuth kernel reads strips of adjacent
+ *                  azimuth lines straight from the range pass's [Na][Nr]
+ *                  output (FP32, Na <= 4096, transpose_back = 0; else
+ *                  SAR_ERR_UNSUPPORTED).  Images are bit-identical to
+ *                  SAR_FUSED's; the step entry points behave as for
+ *                  SAR_FUSED.
  *  transpose_back  0: sar_rda_execute leaves the image as [Nr][Na];
  *                  1: it is turned back to [Na][Nr].
  */
@@ -188,19 +196,20 @@ sar_status sar_rda_execute(sar_plan_t plan, const void* raw_dev, void* img_dev,
 sar_status sar_rda_execute_noalloc(sar_plan_t plan, const void* raw_dev, void* img_dev,
                                    void* stream);
 
-/* Measurement (the per-kernel durations the benchmark reports, Sec. V.C
- * Table III's per-step breakdown): the next kernel launched by the library on
- * the calling thread records start_event when that kernel starts and
- * stop_event when it ends.  The timestamps come from the kernel's own
- * dispatch (hipExtLaunchKernel), so their interval is the kernel's duration
- * as a profiler's kernel trace reports it, without the launch gaps that
- * events recorded between launches include.  Both are hipEvent_t the caller
- * created with timing enabled and keeps alive until they have completed;
- * NULL, NULL disarms.  One event given without the other: SAR_ERR_NULL.
- * Each step entry point that launches a single kernel (sar_range_compress
- * and sar_azimuth_fft of a fused FP32 plan, sar_corner_turn,
- * sar_rcmc_azimuth) is thereby timed whole. */
-sar_status sar_time_next_launch(void* start_event, void* stop_event);
+/* Measurement (the per-kernel durations the benchmark reports, the analogue
+ * of Sec. V.C Table III's per-step breakdown): the next n kernels launched by
+ * the library on the calling thread record start_events[i] when kernel i
+ * starts and stop_events[i] when it ends.  The timestamps come from each
+ * kernel's own dispatch (hipExtLaunchKernel), so an interval is the kernel's
+ * duration as a profiler's kernel trace reports it, without the launch gaps
+ * that events recorded between launches include.  The events are
+ * hipEvent_t the caller created with timing enabled and keeps alive until
+ * they have completed.  n = 0 disarms; n outside 0..16 is SAR_ERR_BAD_SIZE,
+ * a NULL array or event SAR_ERR_NULL (nothing armed then).  sar_rda_execute
+ * launches 4 kernels for a fused FP32 hyperbolic plan (range, corner turn,
+ * azimuth FFT, RCMC), 3 for LFM or for SAR_TURN_FREE hyperbolic, 2 for
+ * SAR_TURN_FREE LFM. */
+sar_status sar_time_next_launches(void* const* start_events, void* const* stop_events, int32_t n);
 
 /* ---- individual steps, for step-by-step testing and the unfused path ---- */
 

@@ -10,7 +10,7 @@ from . import _lib
 from ._lib import (SarError, make_params, sar_params, sar_plan, sar_plan_destroy,
                    sar_workspace_bytes, sar_range_compress, sar_corner_turn,
                    sar_azimuth_compress, sar_rda_execute, sar_rda_execute_noalloc,
-                   sar_time_next_launch,
+                   sar_time_next_launch, sar_time_next_launches,
                    sar_fft_lines, sar_azimuth_fft,
                    sar_rcmc_azimuth, sar_plan_get_table, sar_batch_plan,
                    sar_batch_workspace_bytes, sar_batch_execute, sar_batch_destroy,
@@ -20,7 +20,7 @@ from ._lib import (SarError, make_params, sar_params, sar_plan, sar_plan_destroy
 __all__ = ["Plan", "SarError", "make_params", "sar_params", "sar_plan", "sar_plan_destroy",
            "sar_workspace_bytes", "sar_range_compress", "sar_corner_turn",
            "sar_azimuth_compress", "sar_rda_execute", "sar_rda_execute_noalloc",
-           "sar_time_next_launch",
+           "sar_time_next_launch", "sar_time_next_launches",
            "sar_fft_lines", "sar_azimuth_fft",
            "sar_rcmc_azimuth", "sar_plan_get_table", "sar_batch_plan",
            "sar_batch_workspace_bytes", "sar_batch_execute", "sar_batch_destroy",

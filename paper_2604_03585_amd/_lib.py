@@ -48,7 +48,7 @@ STATUS_NAMES = {0: "SAR_OK", 1: "SAR_ERR_NULL", 2: "SAR_ERR_BAD_SIZE", 3: "SAR_E
 
 SAR_AZ_LFM, SAR_AZ_HYPERBOLIC = 0, 1
 SAR_FP32, SAR_SPLIT_FP16, SAR_SPLIT_BF16, SAR_FP32_HALF_STORAGE = 0, 1, 2, 3
-SAR_FUSED, SAR_UNFUSED = 0, 1
+SAR_FUSED, SAR_UNFUSED, SAR_TURN_FREE = 0, 1, 2
 
 TABLE_HR, TABLE_HA, TABLE_STRETCH, TABLE_RATE, TABLE_RCMC = 0, 1, 2, 3, 4
 RCMC_INTERVALS = 128
@@ -99,7 +99,8 @@ _sar_corner_turn = _fn("sar_corner_turn", [_vp, _vp, _vp, ctypes.c_int32, ctypes
 _sar_azimuth_compress = _fn("sar_azimuth_compress", [_vp, _vp, _vp, _vp, _vp])
 _sar_rda_execute = _fn("sar_rda_execute", [_vp, _vp, _vp, _vp, _vp])
 _sar_rda_execute_noalloc = _fn("sar_rda_execute_noalloc", [_vp, _vp, _vp, _vp])
-_sar_time_next_launch = _fn("sar_time_next_launch", [_vp, _vp])
+_sar_time_next_launches = _fn("sar_time_next_launches",
+                             [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int32])
 _sar_fft_lines = _fn("sar_fft_lines", [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
                                        ctypes.c_int32, _vp])
 _sar_azimuth_fft = _fn("sar_azimuth_fft", [_vp, _vp, _vp, _vp])
@@ -164,7 +165,7 @@ def sar_version() -> str:
 _AZ = {"lfm": SAR_AZ_LFM, "hyperbolic": SAR_AZ_HYPERBOLIC}
 _PREC = {"fp32": SAR_FP32, "split_fp16": SAR_SPLIT_FP16, "split_bf16": SAR_SPLIT_BF16,
          "fp32_halfstore": SAR_FP32_HALF_STORAGE}
-_SCHED = {"fused": SAR_FUSED, "unfused": SAR_UNFUSED}
+_SCHED = {"fused": SAR_FUSED, "unfused": SAR_UNFUSED, "turn_free": SAR_TURN_FREE}
 
 
 def make_params(cfg: dict, precision="fp32", schedule="fused", transpose_back=0) -> sar_params:
@@ -226,20 +227,32 @@ def sar_rda_execute(plan, raw_dev, img_dev, work_dev, stream=None):
                             _stream(stream)), "sar_rda_execute")
 
 
-def sar_time_next_launch(start_event, stop_event):
-    """Arm two events (torch.cuda.Event with timing, or raw hipEvent_t handles;
-    None, None disarms) for the next kernel launch on this thread.  A torch
-    event whose handle does not exist yet is created by recording it once."""
+def sar_time_next_launches(starts, stops):
+    """Arm pairs of events for the next len(starts) kernel launches on this
+    thread (torch.cuda.Event with timing, or raw hipEvent_t handles; empty
+    lists disarm).  A torch event whose handle does not exist yet is created
+    by recording it once on the current stream."""
     def handle(e):
-        if e is None:
-            return None
         if hasattr(e, "cuda_event"):
             if not e.cuda_event:
                 import torch
                 e.record(torch.cuda.current_stream())
             return int(e.cuda_event)
-        return int(e)
-    _check(_sar_time_next_launch(handle(start_event), handle(stop_event)), "sar_time_next_launch")
+        return int(e) if e is not None else None
+    if len(starts) != len(stops):
+        raise ValueError("starts and stops differ in length")
+    n = len(starts)
+    a = (_vp * max(n, 1))(*[handle(e) for e in starts])
+    b = (_vp * max(n, 1))(*[handle(e) for e in stops])
+    _check(_sar_time_next_launches(a, b, n), "sar_time_next_launches")
+
+
+def sar_time_next_launch(start_event, stop_event):
+    """sar_time_next_launches for one launch (None, None disarms)."""
+    if start_event is None and stop_event is None:
+        sar_time_next_launches([], [])
+    else:
+        sar_time_next_launches([start_event], [stop_event])
 
 
 def sar_rda_execute_noalloc(plan, raw_dev, img_dev, stream=None):

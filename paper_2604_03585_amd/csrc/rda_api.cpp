@@ -101,16 +101,18 @@ void setup_noalloc_scratch(int device)
 }  // namespace
 
 namespace {
-thread_local hipEvent_t g_time_start = nullptr, g_time_stop = nullptr;
+constexpr int MAX_TIMED = 16;
+thread_local hipEvent_t g_time_start[MAX_TIMED], g_time_stop[MAX_TIMED];
+thread_local int g_time_next = 0, g_time_count = 0;
 }  // namespace
 
 namespace sar {
 bool take_launch_events(hipEvent_t& start, hipEvent_t& stop)
 {
-    if (!g_time_start) return false;
-    start = g_time_start;
-    stop = g_time_stop;
-    g_time_start = g_time_stop = nullptr;
+    if (g_time_next >= g_time_count) return false;
+    start = g_time_start[g_time_next];
+    stop = g_time_stop[g_time_next];
+    if (++g_time_next == g_time_count) g_time_next = g_time_count = 0;
     return true;
 }
 
@@ -206,8 +208,12 @@ sar_status validate_params(const sar_params* p)
     }
     if (p->precision < SAR_FP32 || p->precision > SAR_FP32_HALF_STORAGE)
         return fail(SAR_ERR_BAD_PARAM, "precision=%d unknown", p->precision);
-    if (p->schedule != SAR_FUSED && p->schedule != SAR_UNFUSED)
+    if (p->schedule != SAR_FUSED && p->schedule != SAR_UNFUSED && p->schedule != SAR_TURN_FREE)
         return fail(SAR_ERR_BAD_PARAM, "schedule=%d unknown", p->schedule);
+    if (p->schedule == SAR_TURN_FREE &&
+        (p->precision != SAR_FP32 || p->transpose_back != 0 || p->Na > 4096))
+        return fail(SAR_ERR_UNSUPPORTED,
+                    "the turn-free schedule runs FP32 with Na <= 4096 and transpose_back = 0");
     if (p->transpose_back != 0 && p->transpose_back != 1)
         return fail(SAR_ERR_BAD_PARAM, "transpose_back must be 0 or 1");
     if (p->precision == SAR_FP32_HALF_STORAGE) {
@@ -271,7 +277,7 @@ namespace {
 sar_status step_range(const sar_plan_s* P, const void* in, void* out, hipStream_t s)
 {
     const int Nr = P->p.Nr, Na = P->p.Na;
-    if (P->p.schedule == SAR_FUSED) {
+    if (P->p.schedule != SAR_UNFUSED) {
         HIP_TRY(sar::launch_line(LineOp::Fused, Nr, in, out, Na, P->Hr, P->tw_r, 1.f, nullptr, arith(P),
                                  P->var_r[sar::TK_FUSED], s),
                 "range fused launch");
@@ -298,7 +304,7 @@ sar_status step_azimuth(const sar_plan_s* P, const void* in, void* out, void* wo
 {
     const int Nr = P->p.Nr, Na = P->p.Na;
     if (P->p.az_model == SAR_AZ_LFM) {
-        if (P->p.schedule == SAR_FUSED) {
+        if (P->p.schedule != SAR_UNFUSED) {
             HIP_TRY(sar::launch_line(LineOp::Fused, Na, in, out, Nr, P->Ha, P->tw_a, 1.f, nullptr,
                                      arith(P), P->var_a[sar::TK_FUSED], s),
                     "azimuth fused launch");
@@ -317,7 +323,7 @@ sar_status step_azimuth(const sar_plan_s* P, const void* in, void* out, void* wo
     HIP_TRY(sar::launch_line(LineOp::Forward, Na, in, work, Nr, nullptr, P->tw_a, 1.f, nullptr,
                              arith(P), P->var_a[sar::TK_FWD], s),
             "azimuth FFT launch");
-    if (P->p.schedule == SAR_FUSED) {
+    if (P->p.schedule != SAR_UNFUSED) {
         HIP_TRY(sar::launch_line(LineOp::RcmcAz, Na, work, out, Nr, nullptr, P->tw_a, 1.f, &rh,
                                  arith(P), P->var_a[sar::TK_RCMC], s),
                 "RCMC+azimuth launch");
@@ -328,6 +334,32 @@ sar_status step_azimuth(const sar_plan_s* P, const void* in, void* out, void* wo
                                      arith(P), P->var_a[sar::TK_INV], s),
                 "azimuth IFFT launch");
     }
+    return SAR_OK;
+}
+
+// Turn-free schedule: no corner turn.  The azimuth pass reads strips of
+// adjacent azimuth lines straight from the range pass's [Na][Nr] output.
+//   LFM:        raw -> range -> work [Na][Nr] -> strips FFT*H*IFFT -> img [Nr][Na]
+//   hyperbolic: raw -> range -> img [Na][Nr] -> strips FFT -> work [Nr][Na]
+//               -> RCMC*phase*IFFT -> img [Nr][Na]
+sar_status execute_turn_free(const sar_plan_s* P, const void* raw, void* img, void* work,
+                             hipStream_t s)
+{
+    const int Nr = P->p.Nr, Na = P->p.Na;
+    sar_status st;
+    if (P->p.az_model == SAR_AZ_LFM) {
+        if ((st = step_range(P, raw, work, s))) return st;
+        HIP_TRY(sar::launch_line_strip(true, Na, work, img, Nr, Nr, P->Ha, P->tw_a, 1.f, s),
+                "azimuth strip launch");
+        return SAR_OK;
+    }
+    if ((st = step_range(P, raw, img, s))) return st;
+    HIP_TRY(sar::launch_line_strip(false, Na, img, work, Nr, Nr, nullptr, P->tw_a, 1.f, s),
+            "azimuth strip FFT launch");
+    const sar::RcmcHost rh = rcmc_host(P);
+    HIP_TRY(sar::launch_line(LineOp::RcmcAz, Na, work, img, Nr, nullptr, P->tw_a, 1.f, &rh, arith(P),
+                             P->var_a[sar::TK_RCMC], s),
+            "RCMC+azimuth launch");
     return SAR_OK;
 }
 
@@ -517,6 +549,7 @@ sar_status sar_rda_execute(sar_plan_t P, const void* raw, void* img, void* work,
         return fail(SAR_ERR_ALIAS, "raw, img and work must be pairwise disjoint");
     hipStream_t s = (hipStream_t)stream;
     if (P->p.precision == SAR_FP32_HALF_STORAGE) return execute_half(P, raw, img, work, s);
+    if (P->p.schedule == SAR_TURN_FREE) return execute_turn_free(P, raw, img, work, s);
     const int Nr = P->p.Nr, Na = P->p.Na;
     const bool back = P->p.transpose_back != 0;
     // Buffers alternate so that the last step writes img.
@@ -538,13 +571,22 @@ sar_status sar_rda_execute(sar_plan_t P, const void* raw, void* img, void* work,
     return SAR_OK;
 }
 
-sar_status sar_time_next_launch(void* start_event, void* stop_event)
+sar_status sar_time_next_launches(void* const* start_events, void* const* stop_events, int32_t n)
 {
     g_err.clear();
-    if (!start_event != !stop_event)
-        return fail(SAR_ERR_NULL, "sar_time_next_launch: give both events or neither");
-    g_time_start = (hipEvent_t)start_event;
-    g_time_stop = (hipEvent_t)stop_event;
+    g_time_next = g_time_count = 0;
+    if (n == 0) return SAR_OK;
+    if (n < 0 || n > MAX_TIMED)
+        return fail(SAR_ERR_BAD_SIZE, "sar_time_next_launches: n=%d outside 0..%d", n, MAX_TIMED);
+    if (!start_events || !stop_events) return fail(SAR_ERR_NULL, "sar_time_next_launches: NULL array");
+    for (int i = 0; i < n; ++i)
+        if (!start_events[i] || !stop_events[i])
+            return fail(SAR_ERR_NULL, "sar_time_next_launches: event %d is NULL", i);
+    for (int i = 0; i < n; ++i) {
+        g_time_start[i] = (hipEvent_t)start_events[i];
+        g_time_stop[i] = (hipEvent_t)stop_events[i];
+    }
+    g_time_count = n;
     return SAR_OK;
 }
 

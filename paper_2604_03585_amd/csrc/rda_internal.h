@@ -16,8 +16,8 @@ namespace sar {
 sar_status set_error(sar_status st, const char* fmt, ...);
 void clear_error();
 
-// The events sar_time_next_launch armed on this thread, if any: taken (and
-// disarmed) by the next kernel launch, which records them at its start and
+// The next pair of events sar_time_next_launches armed on this thread, if
+// any: taken by the next kernel launch, which records them at its start and
 // end.
 bool take_launch_events(hipEvent_t& start, hipEvent_t& stop);
 
@@ -69,6 +69,14 @@ hipError_t launch_line(LineOp op, int n, const void* in, void* out, int lines, c
                        const void* tw, float scale, const RcmcHost* rh, int prec, int variant,
                        hipStream_t s);
 int twiddle_table_size(int n);
+
+// Column-strip azimuth pass (turn-free schedule, FP32, n <= 4096): the n-point
+// azimuth lines of range cells 0 .. cols-1, read from in [n][pitch] (the range
+// pass's output), transformed (fused: IFFT(FFT * H); else FFT * scale) and
+// stored as lines out [cols][n].  cols must be a multiple of the strip width
+// min(16, 1024 / (n / 16)).
+hipError_t launch_line_strip(bool fused, int n, const void* in, void* out, int cols, int pitch,
+                             const void* H, const void* tw, float scale, hipStream_t s);
 
 // Batched launches (kind: 0 fused, 1 forward, 2 inverse; tasks in device memory).
 //  variant bits 0 (twiddles) and 2-3 (grid: one workgroup per line group, or

@@ -197,24 +197,16 @@ enum LineKind { LK_FUSED = 0, LK_FWD = 1, LK_INV = 2 };
 // twiddles by products (true) or straight table reads (false), chosen per
 // line length by the autotuner; SPLIT (FP32 forward / inverse): the split
 // real/imaginary exchange layout.
+// The transform of one line held by its T threads (thread t: points t + m*T)
+// with `lds` its exchange buffer: FFT * H * IFFT, FFT or IFFT (see line_group).
 template <int N, int KIND, int PREC, bool TWP, bool SPLIT = false>
-__device__ __forceinline__ void line_group(const float2* in, float2* out, int lines,
-                                           const float2* __restrict__ H,
-                                           const float2* __restrict__ tw, float scale, int g,
-                                           float2* smem)
+__device__ __forceinline__ void line_transform(float2 (&x)[line_e(N)], float2* __restrict__ lds,
+                                               const float2* __restrict__ H,
+                                               const float2* __restrict__ tw, float scale,
+                                               int sub, int t)
 {
     using L = LineLaunch<N>;
     constexpr int E = line_e(N);
-    const int sub = threadIdx.x / L::T, t = threadIdx.x % L::T;
-    const int line = g * L::LPW + sub;
-    const bool live = line < lines;
-    float2* lds = smem + sub * LineGeom<N>::LDS;
-    float2 x[E];
-    if (live) load_line<N>(x, in + (size_t)line * N, t);
-    else {
-#pragma unroll
-        for (int m = 0; m < E; ++m) x[m] = make_float2(0.f, 0.f);
-    }
     if constexpr (KIND == LK_FUSED) {
         // the filter is requested just before the last forward pass.  Lines
         // of 8192 points and more (one or two workgroups per CU) read their
@@ -241,7 +233,78 @@ __device__ __forceinline__ void line_group(const float2* in, float2* out, int li
             for (int m = 0; m < E; ++m) x[m] = c_scale(x[m], scale);
         }
     }
+}
+
+template <int N, int KIND, int PREC, bool TWP, bool SPLIT = false>
+__device__ __forceinline__ void line_group(const float2* in, float2* out, int lines,
+                                           const float2* __restrict__ H,
+                                           const float2* __restrict__ tw, float scale, int g,
+                                           float2* smem)
+{
+    using L = LineLaunch<N>;
+    constexpr int E = line_e(N);
+    const int sub = threadIdx.x / L::T, t = threadIdx.x % L::T;
+    const int line = g * L::LPW + sub;
+    const bool live = line < lines;
+    float2* lds = smem + sub * LineGeom<N>::LDS;
+    float2 x[E];
+    if (live) load_line<N>(x, in + (size_t)line * N, t);
+    else {
+#pragma unroll
+        for (int m = 0; m < E; ++m) x[m] = make_float2(0.f, 0.f);
+    }
+    line_transform<N, KIND, PREC, TWP, SPLIT>(x, lds, H, tw, scale, sub, t);
     if (live) store_line<N>(x, out + (size_t)line * N, t);
+}
+
+// ---------------------------------------------------------- column strips
+// Turn-free schedule: the azimuth lines of a strip of C adjacent range cells
+// read straight from the range pass's [Na][Nr] output, so no corner turn is
+// needed.  Each row of the strip is C consecutive samples (C * 8 bytes: 32 B
+// at 4096 points, 64 B at 2048, 128 B at 1024 and below); the workgroup
+// reads the C x N strip with consecutive lanes on consecutive samples,
+// regroups it through LDS into one line per slot of T = N/16 threads, runs
+// the same line transform as k_line (so the results are bit-identical to
+// the turned path) and stores each line contiguously: out is [Nr][Na].
+// C = min(16, 1024 / T) lines per workgroup (N <= 4096: 136 KiB of LDS).
+template <int N> struct StripLaunch {
+    static constexpr int T = LineGeom<N>::T;
+    static constexpr int C = (1024 / T) < 16 ? 1024 / T : 16;
+    static constexpr int BLOCK = C * T;
+    // line buffers 16 float2 more than a line's exchange buffer apart, so
+    // the C samples of one row (consecutive lanes) fall into different banks
+    static constexpr int STRIDE = LineGeom<N>::LDS + 16;
+    static constexpr int LDS_BYTES = C * STRIDE * (int)sizeof(float2);
+    static_assert(N <= 4096 && C >= 4, "strips of at least four lines");
+};
+
+template <int N, int KIND, bool TWP>
+__global__ __launch_bounds__(StripLaunch<N>::BLOCK) void
+k_line_strip(const float2* __restrict__ in, float2* __restrict__ out, int cols, int pitch,
+             const float2* __restrict__ H, const float2* __restrict__ tw, float scale)
+{
+    using S = StripLaunch<N>;
+    constexpr int T = S::T, C = S::C, E = line_e(N);
+    static_assert(S::BLOCK * E == C * N, "one sample per thread and pass");
+    extern __shared__ __align__(16) float2 smem[];
+    const int g = xcd_group(blockIdx.x, cols / C);
+    const int n0 = g * C;
+    const int u = threadIdx.x;
+#pragma unroll
+    for (int p = 0; p < E; ++p) {
+        const int e = u + p * S::BLOCK;           // sample (row m, column c) of the strip
+        const int m = e / C, c = e % C;
+        smem[c * S::STRIDE + lds_pad(m)] = in[(size_t)m * pitch + n0 + c];
+    }
+    __syncthreads();
+    const int sub = u / T, t = u % T;
+    float2* lds = smem + sub * S::STRIDE;
+    float2 x[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) x[m] = lds[lds_pad(t + m * T)];
+    __syncthreads();                              // reads done before the exchanges
+    line_transform<N, KIND, PREC_FP32, TWP>(x, lds, H, tw, scale, sub, t);
+    store_line<N>(x, out + (size_t)(n0 + sub) * N, t);
 }
 
 template <int N, int KIND, int PREC, bool TWP, bool SPLIT = false>
@@ -1481,6 +1544,53 @@ hipError_t launch_line_fp32(LineOp op, int n, const float2* i, float2* o, int li
                             int taps, int v, hipStream_t s)
 {
     return launch_line_prec<PREC_FP32>(op, n, i, o, lines, h, w, scale, ra, taps, v, s);
+}
+
+template <int N, int KIND>
+static hipError_t launch_strip_k(const float2* in, float2* out, int cols, int pitch,
+                                 const float2* H, const float2* tw, float scale, hipStream_t s)
+{
+    using S = StripLaunch<N>;
+    static const hipError_t attr =
+        S::LDS_BYTES <= 64 * 1024
+            ? hipSuccess
+            : hipFuncSetAttribute((const void*)k_line_strip<N, KIND, true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, S::LDS_BYTES);
+    if (attr != hipSuccess) return attr;
+    if (cols % S::C != 0) return hipErrorInvalidValue;
+    if (cols == 0) return hipSuccess;
+    SAR_LAUNCH((k_line_strip<N, KIND, true>), dim3(cols / S::C), dim3(S::BLOCK), S::LDS_BYTES, s,
+               in, out, cols, pitch, H, tw, scale);
+    return hipGetLastError();
+}
+
+// Twiddles by products only: the strips' 1024-thread workgroups hold 128
+// VGPRs, where the table-twiddle transforms spill.
+template <int N>
+static hipError_t launch_strip_n(bool fused, const float2* in, float2* out, int cols, int pitch,
+                                 const float2* H, const float2* tw, float scale, hipStream_t s)
+{
+    if (fused) return launch_strip_k<N, LK_FUSED>(in, out, cols, pitch, H, tw, 1.f, s);
+    return launch_strip_k<N, LK_FWD>(in, out, cols, pitch, nullptr, tw, scale, s);
+}
+
+hipError_t launch_line_strip(bool fused, int n, const void* in, void* out, int cols, int pitch,
+                             const void* H, const void* tw, float scale, hipStream_t s)
+{
+    auto i = (const float2*)in;
+    auto o = (float2*)out;
+    auto h = (const float2*)H;
+    auto w = (const float2*)tw;
+    switch (n) {
+    case 64: return launch_strip_n<64>(fused, i, o, cols, pitch, h, w, scale, s);
+    case 128: return launch_strip_n<128>(fused, i, o, cols, pitch, h, w, scale, s);
+    case 256: return launch_strip_n<256>(fused, i, o, cols, pitch, h, w, scale, s);
+    case 512: return launch_strip_n<512>(fused, i, o, cols, pitch, h, w, scale, s);
+    case 1024: return launch_strip_n<1024>(fused, i, o, cols, pitch, h, w, scale, s);
+    case 2048: return launch_strip_n<2048>(fused, i, o, cols, pitch, h, w, scale, s);
+    case 4096: return launch_strip_n<4096>(fused, i, o, cols, pitch, h, w, scale, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <const void* (*KERNEL)(), int BYTES>

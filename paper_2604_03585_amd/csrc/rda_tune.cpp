@@ -340,7 +340,7 @@ sar_status sar_autotune(const sar_params* p, const char* cache_path)
               prec = p->precision == SAR_FP32_HALF_STORAGE ? SAR_FP32 : p->precision;
     const bool fp32 = prec == SAR_FP32;
     const bool hyper = p->az_model == SAR_AZ_HYPERBOLIC;
-    const bool fused = p->schedule == SAR_FUSED;
+    const bool fused = p->schedule != SAR_UNFUSED;   // turn-free runs the fused kernels
     const size_t bytes = (size_t)Na * (size_t)Nr * 8;
     void *in = nullptr, *out = nullptr, *task = nullptr;
     hipStream_t s = nullptr;

@@ -132,8 +132,23 @@ def test_noalloc_rejects_null_plan():
     assert e.value.status == _lib.SAR_ERR_NULL
 
 
-def test_time_next_launch_wants_both_events_or_neither():
+def test_time_next_launches_checks_its_arguments():
     with pytest.raises(sar.SarError) as e:
         sar.sar_time_next_launch(16, None)
     assert e.value.status == _lib.SAR_ERR_NULL
+    with pytest.raises(sar.SarError) as e:
+        sar.sar_time_next_launches([16] * 17, [32] * 17)
+    assert e.value.status == _lib.SAR_ERR_BAD_SIZE
     sar.sar_time_next_launch(None, None)     # disarm: always fine, no GPU call
+    sar.sar_time_next_launches([], [])
+
+
+@pytest.mark.parametrize("change", [dict(precision=1), dict(precision=3), dict(transpose_back=1),
+                                    dict(Na=8192)])
+def test_turn_free_limits_are_unsupported(change):
+    cfg = config("c1", **({"Na": change["Na"], "az_len": 64} if "Na" in change else {}))
+    p = sar.make_params(cfg, schedule="turn_free")
+    for k, v in change.items():
+        if k != "Na":
+            setattr(p, k, v)
+    assert _status(p) == _lib.SAR_ERR_UNSUPPORTED

@@ -42,7 +42,7 @@ def run_gpu(cfg, raw, schedule="fused", transpose_back=0):
 
 
 @pytest.mark.parametrize("name", ["c1", "c2"])
-@pytest.mark.parametrize("schedule", ["fused", "unfused"])
+@pytest.mark.parametrize("schedule", ["fused", "unfused", "turn_free"])
 def test_rda_parity(name, schedule):
     cfg, sc, ref = scene_and_oracle(name)
     img = run_gpu(cfg, sc.raw, schedule)
@@ -121,3 +121,39 @@ def test_noise_only_scene():
     cfg, sc, ref = scene_and_oracle("c1", n_targets=0)
     img = run_gpu(cfg, sc.raw)
     assert rel_l2(img, ref) <= TOL_RDA
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_turn_free_bit_identical_to_fused(name):
+    """The turn-free schedule reads strips of azimuth lines straight from the
+    range output instead of turning it; the butterflies are the same, so the
+    image equals the fused schedule's bit for bit."""
+    cfg, sc, _ = scene_and_oracle(name)
+    a = np.ascontiguousarray(run_gpu(cfg, sc.raw, "fused"))
+    b = np.ascontiguousarray(run_gpu(cfg, sc.raw, "turn_free"))
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+@pytest.mark.parametrize("nr, na, model", [(64, 64, "c1"), (4096, 64, "c1"), (64, 4096, "c1"),
+                                           (128, 2048, "c1"), (1024, 512, "c1"),
+                                           (512, 4096, "c2"), (1024, 1024, "c2"),
+                                           (256, 2048, "c2")])
+def test_turn_free_shapes(nr, na, model):
+    """Every strip width (16 lines up to 1024 points, 8 at 2048, 4 at 4096)
+    and the narrowest scenes, LFM and hyperbolic, against the oracle and bit
+    for bit against the fused schedule."""
+    if model == "c1":
+        cfg = config("c1", Nr=nr, Na=na, range_len=min(64, nr // 2), range_tbp=min(32, nr // 4),
+                     az_len=min(64, na // 2), az_tbp=min(32, na // 4), n_targets=1, spacing=4)
+    else:
+        lr = min(512, nr // 2)
+        cfg = config("c2", Nr=nr, Na=na, range_len=lr, range_tbp=min(200.0, lr / 2.0),
+                     n_targets=1, spacing=8, exposure=min(1024, na // 2))
+    sc = simulate(cfg)
+    ref = O.rda(sc.raw, cfg)
+    img = run_gpu(cfg, sc.raw, "turn_free")
+    err = rel_l2(img, ref)
+    print(f"turn-free {model} {nr}x{na}: rel L2 {err:.3e}")
+    assert err <= TOL_RDA
+    fused = np.ascontiguousarray(run_gpu(cfg, sc.raw, "fused"))
+    assert np.array_equal(np.ascontiguousarray(img).view(np.uint32), fused.view(np.uint32))
