@@ -253,7 +253,9 @@ sar_status sar_plan_get_table(sar_plan_t plan, int32_t which, void* host_dst,
  * other scene (hyperbolic, unfused, half storage, and any scene of 2^22
  * pixels or more, which fills the GPU with its own launches) runs as
  * sar_rda_execute in the same stream, in scene order, after the shared
- * launches.  Each scene's image is bit-identical to its own sar_rda_execute.
+ * launches; those of 2^22 pixels or more with the fused schedule in FP32,
+ * Na <= 4096 and no back-turn run the turn-free kernels (SAR_TURN_FREE).
+ * Each scene's image is bit-identical to its own sar_rda_execute.
  */
 
 /* Plan `n` scenes (params ps[0..n-1], n >= 1): validates every parameter set

@@ -12,7 +12,8 @@
 // Scenes whose processing the batched launches do not cover (hyperbolic
 // azimuth, the unfused schedule, half storage) and scenes large enough to
 // fill the chip alone (see kShareBelowPx) run through sar_rda_execute inside
-// the same stream (and graph).
+// the same stream (and graph); the large fused FP32 ones that the turn-free
+// kernels cover run those (bit-identical, without the corner turn).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -94,6 +95,19 @@ bool batched(const sar_params& p)
 {
     return p.az_model == SAR_AZ_LFM && p.schedule == SAR_FUSED && p.precision != SAR_FP32_HALF_STORAGE &&
            (long long)p.Na * p.Nr < kShareBelowPx;
+}
+
+// The parameters a scene's own plan is built with.  A fused FP32 scene that
+// runs alone (4 Mpx or more) and that the turn-free kernels cover (Na <=
+// 4096, no back-turn) runs them: the same image bit for bit, without its
+// corner turn (32 instead of 48 B/px for LFM, 48 instead of 64 hyperbolic).
+sar_params own_plan_params(const sar_params& p)
+{
+    sar_params q = p;
+    if (p.schedule == SAR_FUSED && p.precision == SAR_FP32 && p.transpose_back == 0 &&
+        p.Na <= 4096 && (long long)p.Na * p.Nr >= kShareBelowPx)
+        q.schedule = SAR_TURN_FREE;
+    return q;
 }
 
 // Build task arrays for this buffer set and upload them (synchronous).
@@ -245,7 +259,8 @@ sar_status sar_batch_plan(const sar_params* ps, int32_t n, void* stream, sar_bat
             if (same_params(distinct[j], ps[i])) idx = (int)j;
         if (idx < 0) {
             sar_plan_t P = nullptr;
-            sar_status st = sar_plan(&ps[i], stream, &P);
+            const sar_params q = own_plan_params(ps[i]);
+            sar_status st = sar_plan(&q, stream, &P);
             if (st != SAR_OK) {
                 for (auto q : B->plans) sar_plan_destroy(q);
                 delete B;
