@@ -10,8 +10,11 @@
 // with v_mfma_f32_16x16x32_{f16,bf16}: D(16x16) = A(16x32) B(32x16), where a
 // wave's lane l holds A[l%16][8(l/16)+i], B[8(l/16)+i][l%16] (i < 8) and
 // D[4(l/16)+i][l%16] (i < 4) -- the layout was checked on the device.  The
-// first MFMA of each half gives Yr (A = [Fr -Fi]), the second Yi
-// (A = [Fi Fr]); B is [Xr; Xi] for 16 butterflies.
+// rows of B interleave the parts, B[2n][b] = Re x_n, B[2n+1][b] = Im x_n of
+// butterfly b, and the columns of A follow: one MFMA gives Yr (A[k][2n] =
+// Fr, A[k][2n+1] = -Fi), the other Yi (Fi, Fr).  A lane's B values are then
+// the complete samples x_4q .. x_4q+3 (q = l/16), four 8-byte LDS reads, and
+// its D values the complete outputs Y_4q .. Y_4q+3, four 8-byte writes.
 //
 // Each FP32 operand is split as x = hi + lo (hi = round(x), lo =
 // round(x - hi)) and the product is accumulated in FP32 as
@@ -29,8 +32,8 @@
 // FP32 between passes, on the output side of a pass (where a lane holds
 // complete complex values), already for the next pass.
 //
-// LDS holds the WG's lines in split form: re[] then im[], one pad slot per 16
-// entries, the same bytes as the float2 layout of the FP32 path.
+// LDS holds the WG's lines as complex values (float2), one pad slot per 16
+// entries: the exchange layout of the FP32 path.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -63,17 +66,32 @@ template <> struct MfmaT<PREC_BF16> {
     }
 };
 
-// hi + lo split of eight FP32 values.
+typedef float f8_t __attribute__((ext_vector_type(8)));
+
+// hi + lo split of eight FP32 values: hi = round(v) by packed conversions,
+// lo = round(v - hi), where v - hi is exact in FP32 (hi is v rounded to
+// fewer bits in the same binade or a subnormal).  FP16: v - hi is one
+// v_fma_mix_f32 per value (hi widened inside the FMA, times a -1 held in a
+// register so that the compiler keeps the mixed form); BF16: hi widens by a
+// shift, so a plain subtraction.
 template <int PREC>
 __device__ __forceinline__ void split8(const float (&v)[8], typename MfmaT<PREC>::vec& hi,
                                        typename MfmaT<PREC>::vec& lo)
 {
     using S = typename MfmaT<PREC>::scalar;
+    using V = typename MfmaT<PREC>::vec;
+    f8_t x;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const S h = (S)v[i];
-        hi[i] = h;
-        lo[i] = (S)(v[i] - (float)h);
+    for (int i = 0; i < 8; ++i) x[i] = v[i];
+    hi = __builtin_convertvector(x, V);
+    if constexpr (PREC == PREC_F16) {
+        int m1 = 0xBC00;                          // -1.0 in FP16
+        asm volatile("" : "+s"(m1));
+        const float neg1 = (float)__builtin_bit_cast(_Float16, (unsigned short)m1);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lo[i] = (S)__builtin_fmaf((float)hi[i], neg1, v[i]);
+    } else {
+        lo = __builtin_convertvector(x - __builtin_convertvector(hi, f8_t), V);
     }
 }
 
@@ -97,13 +115,13 @@ __device__ __forceinline__ DftOperands<PREC> dft16_operands(int lane)
     float ar[8], ai[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const int n = 8 * (q & 1) + i;
+        const int n = 4 * q + (i >> 1);                 // column 8q + i = 2n + (i & 1)
         const int m = (k * n) & 15;
         const float fr = C[m] * 0.0625f;
         const float s = C[(m + 12) & 15] * 0.0625f;    // sin(2 pi m/16) = cos(2 pi (m - 4)/16)
         const float fi = INV ? s : -s;                  // F = exp(-+ i 2 pi m / 16)
-        ar[i] = (q < 2) ? fr : -fi;                     // [Fr -Fi]
-        ai[i] = (q < 2) ? fi : fr;                      // [Fi  Fr]
+        ar[i] = (i & 1) ? -fi : fr;                     // Yr: Fr Re x_n - Fi Im x_n
+        ai[i] = (i & 1) ? fr : fi;                      // Yi: Fi Re x_n + Fr Im x_n
     }
     DftOperands<PREC> d;
     split8<PREC>(ar, d.rh, d.rl);
@@ -123,11 +141,11 @@ __device__ __forceinline__ int mfma_line_exponent(float amax)
 
 // The line's exponent, from the largest |re|, |im| over its T threads: lane
 // segments of a wave when T <= 64, else whole waves combined through the
-// line's LDS pad slots (entries 17 w + 16 of its re[] array, which the passes
-// never touch since mf_pad skips them).  On entry no wave may still read the
+// line's LDS pad slots (entries 17 w + 16 of its line, which the passes never
+// touch since mf_pad skips them).  On entry no wave may still read the
 // workgroup's LDS (the callers end every earlier LDS use with a barrier).
 template <int T, int LL>
-__device__ __forceinline__ int mfma_line_scale_exp(const float2 (&x)[16], float* __restrict__ re,
+__device__ __forceinline__ int mfma_line_scale_exp(const float2 (&x)[16], float2* __restrict__ lds,
                                                    int sub)
 {
     float m = 0.f;
@@ -140,12 +158,12 @@ __device__ __forceinline__ int mfma_line_scale_exp(const float2 (&x)[16], float*
         constexpr int WPL = T / 64;               // waves per line
         static_assert(17 * (WPL - 1) + 16 < LL, "pad slots of the line");
         const int lane = threadIdx.x & 63, wl = (threadIdx.x >> 6) % WPL;
-        float* slots = re + sub * LL;
-        if (lane == 0) slots[17 * wl + 16] = m;
+        float2* slots = lds + sub * LL;
+        if (lane == 0) slots[17 * wl + 16].x = m;
         __syncthreads();
         m = 0.f;
 #pragma unroll
-        for (int w = 0; w < WPL; ++w) m = fmaxf(m, slots[17 * w + 16]);
+        for (int w = 0; w < WPL; ++w) m = fmaxf(m, slots[17 * w + 16].x);
     }
     const int e = mfma_line_exponent(m);
     // a wave holds one line when T >= 64: the exponent is wave-uniform
@@ -157,16 +175,19 @@ __device__ __forceinline__ int mfma_line_scale_exp(const float2 (&x)[16], float*
 // trailing smaller pass (if any) in FP32.  On entry each thread holds its
 // line's x in the strided register layout (see fft_line.hpp); on exit it
 // holds the transform (scaled back to the plain unnormalised DFT).
-//   lds:   the workgroup's LDS (LPW lines, 2*(N + N/16) floats each)
+//   lds:   the workgroup's LDS (LPW lines, N + N/16 float2 each)
 //   sub:   this thread's line within the workgroup, t its index in the line
-template <int N, bool INV, int PREC, int LPW, int BLOCK>
-__device__ __forceinline__ void fft_line_mfma(float2 (&x)[16], float* __restrict__ lds,
-                                              const float2* __restrict__ tw, int sub, int t)
+//   before_last: runs as the last MFMA pass starts (callers issue the loads
+//          they need right after the transform there, e.g. a filter)
+template <int N, bool INV, int PREC, int LPW, int BLOCK, class Pre = NoOp>
+__device__ __forceinline__ void fft_line_mfma(float2 (&x)[16], float2* __restrict__ lds,
+                                              const float2* __restrict__ tw, int sub, int t,
+                                              Pre&& before_last = Pre())
 {
     using G = LineGeom<N, 16>;
     static_assert(line_e(N) == 16, "the MFMA path uses 16 points per thread");
     constexpr int T = G::T;
-    constexpr int LL = G::LDS;                   // floats per component per line
+    constexpr int LL = G::LDS;                   // float2 per line
     constexpr int NB = N / 16;                   // butterflies per line and pass
     constexpr int NMF = G::NFULL;                // radix-16 (MFMA) passes
     constexpr int GROUPS = LPW * NB / 16;        // 16-butterfly groups per workgroup
@@ -174,37 +195,59 @@ __device__ __forceinline__ void fft_line_mfma(float2 (&x)[16], float* __restrict
     constexpr int GPW = GROUPS / WAVES;          // groups per wave
     static_assert(GROUPS % WAVES == 0 && GPW >= 1, "group split");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    float* re = lds;
-    float* im = lds + LPW * LL;
 
-    // registers -> LDS (split), scaled by the line's 2^-ex
-    const int ex = mfma_line_scale_exp<T, LL>(x, re, sub);
+    const int c = lane & 15, q = lane >> 4;
+
+    // registers -> LDS, scaled by the line's 2^-ex
+    const int ex = mfma_line_scale_exp<T, LL>(x, lds, sub);
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-        const int e = sub * LL + mf_pad(t + m * T);
-        re[e] = ldexpf(x[m].x, -ex);
-        im[e] = ldexpf(x[m].y, -ex);
-    }
+    for (int m = 0; m < 16; ++m)
+        lds[sub * LL + mf_pad(t + m * T)] = make_float2(ldexpf(x[m].x, -ex), ldexpf(x[m].y, -ex));
     __syncthreads();
 
     const DftOperands<PREC> F = dft16_operands<PREC, INV>(lane);
-    const int c = lane & 15, q = lane >> 4;
 
 #pragma unroll
     for (int p = 0; p < NMF; ++p) {
+        if (p == NMF - 1) before_last();
         const int NS = p == 0 ? 1 : (p == 1 ? 16 : (p == 2 ? 256 : 4096));
         const bool next_mfma = (p + 1 < NMF);
-        const int NS2 = NS * 16;                 // span of the next pass
-        const int off2 = next_mfma ? G::tw_off(p + 1) : 0;
+        // Next-pass twiddles of a lane's outputs k = 4q .. 4q+3 of butterfly j
+        // (output e = base + k NS, base = (j / NS) 16 NS + j mod NS): with
+        // 16 NS <= N / 16 the row i2 = e / (N/16) is the same for the four k and
+        // the column (e mod N/16) mod 16 NS is j mod NS + k NS, so the twiddles
+        // W^(i2 (j mod NS + k NS)) form a geometric sequence: the first and the
+        // step W^(i2 NS) are read from the table (at the start of the pass, so
+        // that the reads overlap it), the other three are products.  Row 0
+        // needs none (its twiddles are 1); its reads go to the table's row 1.
+        float2 w0[GPW], wst[GPW];
+        bool won[GPW];
+        if (next_mfma) {
+            const float2* tab = tw + G::tw_off(p + 1);
+#pragma unroll
+            for (int gi = 0; gi < GPW; ++gi) {
+                const int b = (wave * GPW + gi) * 16 + c;
+                const int j = b % NB, jm = j & (NS - 1);
+                const int i2 = ((j / NS) * NS * 16 + jm + 4 * q * NS) / NB;
+                const float2* row = tab + (i2 > 0 ? i2 - 1 : 0) * (NS * 16);
+                w0[gi] = row[jm + 4 * q * NS];
+                wst[gi] = row[NS];
+                won[gi] = i2 > 0;
+            }
+        }
         float2 y[GPW][4];
 #pragma unroll
         for (int gi = 0; gi < GPW; ++gi) {
             const int b = (wave * GPW + gi) * 16 + c;          // butterfly in the WG
             const int s = b / NB, j = b % NB;
-            const float* src = (q < 2 ? re : im) + s * LL;
+            const float2* src = lds + s * LL;
             float v[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) v[i] = src[mf_pad(j + (8 * (q & 1) + i) * NB)];
+            for (int h = 0; h < 4; ++h) {
+                const float2 u = src[mf_pad(j + (4 * q + h) * NB)];
+                v[2 * h] = u.x;
+                v[2 * h + 1] = u.y;
+            }
             typename MfmaT<PREC>::vec bh, bl;
             split8<PREC>(v, bh, bl);
             f4_t ar = {0.f, 0.f, 0.f, 0.f}, ai = {0.f, 0.f, 0.f, 0.f};
@@ -214,19 +257,18 @@ __device__ __forceinline__ void fft_line_mfma(float2 (&x)[16], float* __restrict
             ai = MfmaT<PREC>::mma(F.ih, bh, ai);
             ai = MfmaT<PREC>::mma(F.ih, bl, ai);
             ai = MfmaT<PREC>::mma(F.il, bh, ai);
-            const int jm = j & (NS - 1), base = (j / NS) * NS * 16 + jm;
+            float2 w = w0[gi], d = wst[gi];
+            if (INV) {
+                w.y = -w.y;
+                d.y = -d.y;
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 float2 o = make_float2(ar[i], ai[i]);
-                if (next_mfma) {
-                    // pre-twiddle for the next radix-16 pass
-                    const int e = base + (4 * q + i) * NS;
-                    const int j2 = e % NB, i2 = e / NB;
-                    if (i2 > 0) {
-                        float2 w = tw[off2 + (i2 - 1) * NS2 + (j2 & (NS2 - 1))];
-                        if (INV) w.y = -w.y;
-                        o = c_mul(o, w);
-                    }
+                if (next_mfma) {                  // pre-twiddle for the next radix-16 pass
+                    const float2 ow = c_mul(o, w);
+                    o = won[gi] ? ow : o;
+                    if (i < 3) w = c_mul(w, d);
                 }
                 y[gi][i] = o;
             }
@@ -238,11 +280,7 @@ __device__ __forceinline__ void fft_line_mfma(float2 (&x)[16], float* __restrict
             const int s = b / NB, j = b % NB;
             const int base = (j / NS) * NS * 16 + (j & (NS - 1));
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int e = s * LL + mf_pad(base + (4 * q + i) * NS);
-                re[e] = y[gi][i].x;
-                im[e] = y[gi][i].y;
-            }
+            for (int i = 0; i < 4; ++i) lds[s * LL + mf_pad(base + (4 * q + i) * NS)] = y[gi][i];
         }
         __syncthreads();
     }
@@ -251,8 +289,8 @@ __device__ __forceinline__ void fft_line_mfma(float2 (&x)[16], float* __restrict
     const int undo = ex + 4 * NMF;
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
-        const int e = sub * LL + mf_pad(t + m * T);
-        x[m] = make_float2(ldexpf(re[e], undo), ldexpf(im[e], undo));
+        const float2 u = lds[sub * LL + mf_pad(t + m * T)];
+        x[m] = make_float2(ldexpf(u.x, undo), ldexpf(u.y, undo));
     }
     __syncthreads();                              // LDS free for the caller's next use
     if constexpr (G::NP > NMF) {

@@ -158,9 +158,8 @@ __device__ __forceinline__ void fft_any(float2 (&x)[line_e(N)], float2* __restri
         fft_line<N, INV, TWP, SPLIT>(x, lds, tw, t, before_last);
     } else {
         using L = LineLaunch<N>;
-        before_last();
-        fft_line_mfma<N, INV, PREC, L::LPW, L::BLOCK>(x, (float*)(lds - sub * LineGeom<N>::LDS),
-                                                      tw, sub, t);
+        fft_line_mfma<N, INV, PREC, L::LPW, L::BLOCK>(x, lds - sub * LineGeom<N>::LDS, tw, sub,
+                                                      t, before_last);
     }
 }
 
