@@ -73,7 +73,7 @@ typedef float f8_t __attribute__((ext_vector_type(8)));
 // fewer bits in the same binade or a subnormal).  FP16: v - hi is one
 // v_fma_mix_f32 per value (hi widened inside the FMA, times a -1 held in a
 // register so that the compiler keeps the mixed form); BF16: hi widens by a
-// shift, so a plain subtraction.
+// shift or a mask, then a plain subtraction.
 template <int PREC>
 __device__ __forceinline__ void split8(const float (&v)[8], typename MfmaT<PREC>::vec& hi,
                                        typename MfmaT<PREC>::vec& lo)
@@ -91,7 +91,17 @@ __device__ __forceinline__ void split8(const float (&v)[8], typename MfmaT<PREC>
 #pragma unroll
         for (int i = 0; i < 8; ++i) lo[i] = (S)__builtin_fmaf((float)hi[i], neg1, v[i]);
     } else {
-        lo = __builtin_convertvector(x - __builtin_convertvector(hi, f8_t), V);
+        // BF16 widens by placing its bits in the top half of a float: two
+        // bit operations per packed pair
+        typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
+        const u4_t hb = __builtin_bit_cast(u4_t, hi);
+        f8_t back;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            back[2 * i] = __uint_as_float(hb[i] << 16);
+            back[2 * i + 1] = __uint_as_float(hb[i] & 0xffff0000u);
+        }
+        lo = __builtin_convertvector(x - back, V);
     }
 }
 
