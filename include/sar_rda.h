@@ -305,7 +305,13 @@ void sar_batch_destroy(sar_batch_t batch);
  *          (FP32 and Na = 4096 or 8192 only);
  *   kind 4 batched fused line kernel: bit 0 as above, bits 2-3 = grid
  *          (0: one workgroup per line group; 1, 2, 3: a persistent grid of
- *          1x, 2x, 4x the resident workgroups).
+ *          1x, 2x, 4x the resident workgroups);
+ *   kind 5 corner turn, keyed by the row length of the matrix it turns
+ *          (precision 0): variant 0 = a grid of five workgroups per CU,
+ *          1 = four per CU, 2 = one workgroup per 64 x 64 tile;
+ *   kind 6 turn-free azimuth strips, keyed by the azimuth line length
+ *          (precision 0): variant 0 = the default strip width, 1 = half of
+ *          it (half the LDS and threads per workgroup, shorter row runs).
  * The process-wide table starts with every variant 0.  A plan copies the
  * table's choices for its sizes when it is created (sar_plan, sar_batch_plan);
  * the first plan of the process loads $SAR_AUTOTUNE_CACHE if that is set.
@@ -313,12 +319,13 @@ void sar_batch_destroy(sar_batch_t batch);
  * The cache is a JSON-lines text file, one flat object per tuned kernel:
  *   {"arch":"gfx950","kind":"fused","n":4096,"prec":0,"variant":1,
  *    "us_default":64.1,"us_best":61.9}
- * (kind names: "fused", "fwd", "inv", "rcmc", "batch_fused").  Lines for
+ * (kind names: "fused", "fwd", "inv", "rcmc", "batch_fused", "turn", "strip").  Lines for
  * other architectures are preserved; malformed lines are ignored.
  */
 
-/* Time every candidate variant of the kernels a plan of *p launches (and,
- * for fused LFM parameters, the batched fused line kernel for Nr and Na) on
+/* Time every candidate variant of the kernels a plan of *p launches (its
+ * line kernels, its corner turns or turn-free strips, and, for fused LFM
+ * parameters, the batched fused line kernel for Nr and Na) on
  * the current device, interleaving candidates over five timed rounds of eight
  * launches and keeping the best; a variant other than 0 wins only if it is at
  * least 2 % faster.  The winners enter the process-wide table (plans created

@@ -323,7 +323,7 @@ def sar_autotune(params: sar_params, cache_path: str | None = None):
            "sar_autotune")
 
 
-TUNE_FUSED, TUNE_FWD, TUNE_INV, TUNE_RCMC, TUNE_BATCH_FUSED = range(5)
+TUNE_FUSED, TUNE_FWD, TUNE_INV, TUNE_RCMC, TUNE_BATCH_FUSED, TUNE_TURN, TUNE_STRIP = range(7)
 
 
 def sar_tune_load(path: str | None, arch: str | None = None):

@@ -143,6 +143,9 @@ struct sar_plan_s {
     double stretch_max = 0.0;     // hyperbolic: 1/D - 1 at |f| = 1/2
     int var_r[3] = {0, 0, 0};     // tuned variants of the Nr line kernels (fused, fwd, inv)
     int var_a[4] = {0, 0, 0, 0};  // ... of the Na line kernels (fused, fwd, inv, RCMC)
+    int var_turn = 0;             // corner turn of [Na][Nr]
+    int var_back = 0;             // back-turn of [Nr][Na]
+    int var_strip = 0;            // turn-free azimuth strips
 };
 
 namespace {
@@ -293,9 +296,9 @@ sar_status step_range(const sar_plan_s* P, const void* in, void* out, hipStream_
     return SAR_OK;
 }
 
-sar_status step_turn(const void* in, void* out, int rows, int cols, hipStream_t s)
+sar_status step_turn(const void* in, void* out, int rows, int cols, int variant, hipStream_t s)
 {
-    HIP_TRY(sar::launch_corner_turn(in, out, rows, cols, s), "corner turn launch");
+    HIP_TRY(sar::launch_corner_turn(in, out, rows, cols, variant, s), "corner turn launch");
     return SAR_OK;
 }
 
@@ -349,12 +352,13 @@ sar_status execute_turn_free(const sar_plan_s* P, const void* raw, void* img, vo
     sar_status st;
     if (P->p.az_model == SAR_AZ_LFM) {
         if ((st = step_range(P, raw, work, s))) return st;
-        HIP_TRY(sar::launch_line_strip(true, Na, work, img, Nr, Nr, P->Ha, P->tw_a, 1.f, s),
+        HIP_TRY(sar::launch_line_strip(true, Na, work, img, Nr, Nr, P->Ha, P->tw_a, 1.f, P->var_strip, s),
                 "azimuth strip launch");
         return SAR_OK;
     }
     if ((st = step_range(P, raw, img, s))) return st;
-    HIP_TRY(sar::launch_line_strip(false, Na, img, work, Nr, Nr, nullptr, P->tw_a, 1.f, s),
+    HIP_TRY(sar::launch_line_strip(false, Na, img, work, Nr, Nr, nullptr, P->tw_a, 1.f, P->var_strip,
+                                   s),
             "azimuth strip FFT launch");
     const sar::RcmcHost rh = rcmc_host(P);
     HIP_TRY(sar::launch_line(LineOp::RcmcAz, Na, work, img, Nr, nullptr, P->tw_a, 1.f, &rh, arith(P),
@@ -428,6 +432,9 @@ sar_status sar_plan(const sar_params* p, void* stream, sar_plan_t* out)
     const int ap = p->precision == SAR_FP32_HALF_STORAGE ? SAR_FP32 : p->precision;
     for (int k = 0; k < 3; ++k) P->var_r[k] = sar::tuned_variant(k, Nr, ap);
     for (int k = 0; k < 4; ++k) P->var_a[k] = sar::tuned_variant(k, Na, ap);
+    P->var_turn = sar::tuned_variant(sar::TK_TURN, Nr, SAR_FP32);
+    P->var_back = sar::tuned_variant(sar::TK_TURN, Na, SAR_FP32);
+    P->var_strip = sar::tuned_variant(sar::TK_STRIP, Na, SAR_FP32);
     const size_t A = 256;
     size_t off = 0;
     const size_t o_twr = off; off = align_up(off + sizeof(float2) * (size_t)sar::twiddle_table_size(Nr), A);
@@ -519,7 +526,11 @@ sar_status sar_corner_turn(sar_plan_t P, const void* in, void* out, int32_t rows
         return fail(SAR_ERR_BAD_SIZE, "rows=%d cols=%d out of range", rows, cols);
     const size_t n = (size_t)rows * (size_t)cols * 8;
     if (overlap(in, n, out, n)) return fail(SAR_ERR_ALIAS, "corner turn must be out of place");
-    return step_turn(in, out, rows, cols, (hipStream_t)stream);
+    // a plan's own turns use its tuned grid; other shapes the default
+    int v = 0;
+    if (P && rows == P->p.Na && cols == P->p.Nr) v = P->var_turn;
+    else if (P && rows == P->p.Nr && cols == P->p.Na) v = P->var_back;
+    return step_turn(in, out, rows, cols, v, (hipStream_t)stream);
 }
 
 sar_status sar_azimuth_compress(sar_plan_t P, const void* in, void* out, void* work, void* stream)
@@ -556,7 +567,7 @@ sar_status sar_rda_execute(sar_plan_t P, const void* raw, void* img, void* work,
     void* A = back ? img : work;     // range output [Na][Nr]
     void* B = back ? work : img;     // turned [Nr][Na]
     if ((st = step_range(P, raw, A, s))) return st;
-    if ((st = step_turn(A, B, Na, Nr, s))) return st;
+    if ((st = step_turn(A, B, Na, Nr, P->var_turn, s))) return st;
     void* C;                          // azimuth output [Nr][Na]
     if (P->p.az_model == SAR_AZ_LFM) {
         C = B;                        // in place
@@ -566,7 +577,7 @@ sar_status sar_rda_execute(sar_plan_t P, const void* raw, void* img, void* work,
         if ((st = step_azimuth(P, B, C, A, s))) return st;
     }
     if (back) {
-        if ((st = step_turn(C, C == img ? work : img, Nr, Na, s))) return st;
+        if ((st = step_turn(C, C == img ? work : img, Nr, Na, P->var_back, s))) return st;
     }
     return SAR_OK;
 }

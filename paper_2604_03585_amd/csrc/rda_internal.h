@@ -76,7 +76,7 @@ int twiddle_table_size(int n);
 // stored as lines out [cols][n].  cols must be a multiple of the strip width
 // min(16, 1024 / (n / 16)).
 hipError_t launch_line_strip(bool fused, int n, const void* in, void* out, int cols, int pitch,
-                             const void* H, const void* tw, float scale, hipStream_t s);
+                             const void* H, const void* tw, float scale, int variant, hipStream_t s);
 
 // Batched launches (kind: 0 fused, 1 forward, 2 inverse; tasks in device memory).
 //  variant bits 0 (twiddles) and 2-3 (grid: one workgroup per line group, or
@@ -87,7 +87,10 @@ hipError_t launch_line_batch(int kind, int n, const void* tasks, int ntasks, int
 // Autotuned kernel variants, per (kernel kind, line length, precision).  The
 // table starts empty (every variant 0) and is filled by sar_autotune or from a
 // JSON-lines cache named by SAR_AUTOTUNE_CACHE when the first plan is built.
-enum TuneKind { TK_FUSED = 0, TK_FWD = 1, TK_INV = 2, TK_RCMC = 3, TK_BATCH_FUSED = 4 };
+// TK_TURN is keyed by the turned matrix's row length (precision FP32), TK_STRIP
+// by the azimuth line length (FP32).
+enum TuneKind { TK_FUSED = 0, TK_FWD = 1, TK_INV = 2, TK_RCMC = 3, TK_BATCH_FUSED = 4, TK_TURN = 5,
+                TK_STRIP = 6 };
 int tuned_variant(int kind, int n, int prec);
 void load_tune_cache_once();
 
@@ -121,7 +124,8 @@ RcmcHost plan_rcmc(const sar_plan_s* P);   // hyperbolic plans only
 int turn_tiles(int rows, int cols);       // 64 x 64 tiles of a corner turn
 
 hipError_t launch_rowmul(const void* in, void* out, int rows, int n, const void* H, hipStream_t s);
-hipError_t launch_corner_turn(const void* in, void* out, int rows, int cols, hipStream_t s);
+hipError_t launch_corner_turn(const void* in, void* out, int rows, int cols, int variant,
+                              hipStream_t s);
 hipError_t launch_rcmc_interp(const void* A, void* out, int na, const RcmcHost& rh, hipStream_t s);
 hipError_t launch_az_phase(const void* in, void* out, int na, const RcmcHost& rh, float scale,
                            hipStream_t s);

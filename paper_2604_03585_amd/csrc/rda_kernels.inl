@@ -265,24 +265,26 @@ __device__ __forceinline__ void line_group(const float2* in, float2* out, int li
 // regroups it through LDS into one line per slot of T = N/16 threads, runs
 // the same line transform as k_line (so the results are bit-identical to
 // the turned path) and stores each line contiguously: out is [Nr][Na].
-// C = min(16, 1024 / T) lines per workgroup (N <= 4096: 136 KiB of LDS).
-template <int N> struct StripLaunch {
+// C = min(16, 1024 / T) lines per workgroup (N <= 4096: 136 KiB of LDS), or
+// CW lines (the autotuner's half-width candidate).
+template <int N, int CW = 0> struct StripLaunch {
     static constexpr int T = LineGeom<N>::T;
-    static constexpr int C = (1024 / T) < 16 ? 1024 / T : 16;
+    static constexpr int C_DEFAULT = (1024 / T) < 16 ? 1024 / T : 16;
+    static constexpr int C = CW ? CW : C_DEFAULT;
     static constexpr int BLOCK = C * T;
     // line buffers 16 float2 more than a line's exchange buffer apart, so
     // the C samples of one row (consecutive lanes) fall into different banks
     static constexpr int STRIDE = LineGeom<N>::LDS + 16;
     static constexpr int LDS_BYTES = C * STRIDE * (int)sizeof(float2);
-    static_assert(N <= 4096 && C >= 4, "strips of at least four lines");
+    static_assert(N <= 4096 && C >= 2 && C <= C_DEFAULT, "strips of two lines or more");
 };
 
-template <int N, int KIND, bool TWP>
-__global__ __launch_bounds__(StripLaunch<N>::BLOCK) void
+template <int N, int KIND, bool TWP, int CW = 0>
+__global__ __launch_bounds__((StripLaunch<N, CW>::BLOCK)) void
 k_line_strip(const float2* __restrict__ in, float2* __restrict__ out, int cols, int pitch,
              const float2* __restrict__ H, const float2* __restrict__ tw, float scale)
 {
-    using S = StripLaunch<N>;
+    using S = StripLaunch<N, CW>;
     constexpr int T = S::T, C = S::C, E = line_e(N);
     static_assert(S::BLOCK * E == C * N, "one sample per thread and pass");
     extern __shared__ __align__(16) float2 smem[];
@@ -1545,49 +1547,57 @@ hipError_t launch_line_fp32(LineOp op, int n, const float2* i, float2* o, int li
     return launch_line_prec<PREC_FP32>(op, n, i, o, lines, h, w, scale, ra, taps, v, s);
 }
 
-template <int N, int KIND>
+template <int N, int KIND, int CW>
 static hipError_t launch_strip_k(const float2* in, float2* out, int cols, int pitch,
                                  const float2* H, const float2* tw, float scale, hipStream_t s)
 {
-    using S = StripLaunch<N>;
+    using S = StripLaunch<N, CW>;
     static const hipError_t attr =
         S::LDS_BYTES <= 64 * 1024
             ? hipSuccess
-            : hipFuncSetAttribute((const void*)k_line_strip<N, KIND, true>,
+            : hipFuncSetAttribute((const void*)k_line_strip<N, KIND, true, CW>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, S::LDS_BYTES);
     if (attr != hipSuccess) return attr;
     if (cols % S::C != 0) return hipErrorInvalidValue;
     if (cols == 0) return hipSuccess;
-    SAR_LAUNCH((k_line_strip<N, KIND, true>), dim3(cols / S::C), dim3(S::BLOCK), S::LDS_BYTES, s,
-               in, out, cols, pitch, H, tw, scale);
+    SAR_LAUNCH((k_line_strip<N, KIND, true, CW>), dim3(cols / S::C), dim3(S::BLOCK), S::LDS_BYTES,
+               s, in, out, cols, pitch, H, tw, scale);
     return hipGetLastError();
 }
 
 // Twiddles by products only: the strips' 1024-thread workgroups hold 128
-// VGPRs, where the table-twiddle transforms spill.
+// VGPRs, where the table-twiddle transforms spill.  Variant 1: strips of
+// half the default width (C / 2 lines: half the LDS and threads per
+// workgroup, runs of C / 2 samples).
 template <int N>
 static hipError_t launch_strip_n(bool fused, const float2* in, float2* out, int cols, int pitch,
-                                 const float2* H, const float2* tw, float scale, hipStream_t s)
+                                 const float2* H, const float2* tw, float scale, int variant,
+                                 hipStream_t s)
 {
-    if (fused) return launch_strip_k<N, LK_FUSED>(in, out, cols, pitch, H, tw, 1.f, s);
-    return launch_strip_k<N, LK_FWD>(in, out, cols, pitch, nullptr, tw, scale, s);
+    constexpr int HALF = StripLaunch<N>::C_DEFAULT / 2;
+    if (variant == 1) {
+        if (fused) return launch_strip_k<N, LK_FUSED, HALF>(in, out, cols, pitch, H, tw, 1.f, s);
+        return launch_strip_k<N, LK_FWD, HALF>(in, out, cols, pitch, nullptr, tw, scale, s);
+    }
+    if (fused) return launch_strip_k<N, LK_FUSED, 0>(in, out, cols, pitch, H, tw, 1.f, s);
+    return launch_strip_k<N, LK_FWD, 0>(in, out, cols, pitch, nullptr, tw, scale, s);
 }
 
 hipError_t launch_line_strip(bool fused, int n, const void* in, void* out, int cols, int pitch,
-                             const void* H, const void* tw, float scale, hipStream_t s)
+                             const void* H, const void* tw, float scale, int variant, hipStream_t s)
 {
     auto i = (const float2*)in;
     auto o = (float2*)out;
     auto h = (const float2*)H;
     auto w = (const float2*)tw;
     switch (n) {
-    case 64: return launch_strip_n<64>(fused, i, o, cols, pitch, h, w, scale, s);
-    case 128: return launch_strip_n<128>(fused, i, o, cols, pitch, h, w, scale, s);
-    case 256: return launch_strip_n<256>(fused, i, o, cols, pitch, h, w, scale, s);
-    case 512: return launch_strip_n<512>(fused, i, o, cols, pitch, h, w, scale, s);
-    case 1024: return launch_strip_n<1024>(fused, i, o, cols, pitch, h, w, scale, s);
-    case 2048: return launch_strip_n<2048>(fused, i, o, cols, pitch, h, w, scale, s);
-    case 4096: return launch_strip_n<4096>(fused, i, o, cols, pitch, h, w, scale, s);
+    case 64: return launch_strip_n<64>(fused, i, o, cols, pitch, h, w, scale, variant, s);
+    case 128: return launch_strip_n<128>(fused, i, o, cols, pitch, h, w, scale, variant, s);
+    case 256: return launch_strip_n<256>(fused, i, o, cols, pitch, h, w, scale, variant, s);
+    case 512: return launch_strip_n<512>(fused, i, o, cols, pitch, h, w, scale, variant, s);
+    case 1024: return launch_strip_n<1024>(fused, i, o, cols, pitch, h, w, scale, variant, s);
+    case 2048: return launch_strip_n<2048>(fused, i, o, cols, pitch, h, w, scale, variant, s);
+    case 4096: return launch_strip_n<4096>(fused, i, o, cols, pitch, h, w, scale, variant, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1793,7 +1803,8 @@ hipError_t launch_corner_turn_b4(const void* in, void* out, int rows, int cols, 
     return hipGetLastError();
 }
 
-hipError_t launch_corner_turn(const void* in, void* out, int rows, int cols, hipStream_t s)
+hipError_t launch_corner_turn(const void* in, void* out, int rows, int cols, int variant,
+                              hipStream_t s)
 {
     const long long tiles = (long long)((rows + TT - 1) / TT) * ((cols + TT - 1) / TT);
     if (tiles == 0) return hipSuccess;
@@ -1801,8 +1812,12 @@ hipError_t launch_corner_turn(const void* in, void* out, int rows, int cols, hip
                        (((uintptr_t)in | (uintptr_t)out) & 15u) == 0;
     if (whole) {
         // a grid of at most 1280 workgroups (five per CU, as many as LDS
-        // holds), each taking the same number of tiles (the last round ragged)
-        const long long per = (tiles + 1279) / 1280;
+        // holds), each taking the same number of tiles (the last round
+        // ragged); variant 1: at most 1024 (four per CU); variant 2: one
+        // workgroup per tile.  The tiles and their order within a workgroup
+        // do not change the result.
+        const long long cap = variant == 1 ? 1024 : (variant == 2 ? tiles : 1280);
+        const long long per = (tiles + cap - 1) / cap;
         const long long grid = (tiles + per - 1) / per;
         SAR_LAUNCH(k_corner_turn_x2, dim3((unsigned)grid), dim3(256), 0, s,
                            (const float4*)in, (float4*)out, rows, cols, (int)tiles);

@@ -36,8 +36,8 @@
 
 namespace {
 
-const char* const KIND_NAME[] = {"fused", "fwd", "inv", "rcmc", "batch_fused"};
-constexpr int NKIND = 5;
+const char* const KIND_NAME[] = {"fused", "fwd", "inv", "rcmc", "batch_fused", "turn", "strip"};
+constexpr int NKIND = 7;
 
 struct Key {
     int kind, n, prec;
@@ -55,8 +55,12 @@ std::once_flag g_env_once;
 // kernels plus the one-row RCMC kernel only: table twiddles, the split
 // exchange layout and the wide RCMC kernel are FP32 kernels, and the
 // persistent batch grids spill in the split transforms (never faster).
+// The corner turn (grid of five or four workgroups per CU, or one per tile)
+// and the turn-free strips (default or half width) are keyed as FP32.
 bool valid_variant(int kind, int prec, int v)
 {
+    if (kind == sar::TK_TURN) return prec == SAR_FP32 && v >= 0 && v <= 2;
+    if (kind == sar::TK_STRIP) return prec == SAR_FP32 && (v == 0 || v == 1);
     if (prec != SAR_FP32) return v == 0 || (kind == sar::TK_RCMC && v == 2);
     switch (kind) {
     case sar::TK_FUSED: return v == 0 || v == 1;
@@ -436,6 +440,35 @@ sar_status sar_autotune(const sar_params* p, const char* cache_path)
         }
     }
     if (st != SAR_OK) return done(st);
+    // the corner turn(s) of the turned schedules (the half-storage turn moves
+    // FP16 pairs and has no variants)
+    auto tune_turn = [&](int rows, int cols) -> sar_status {
+        for (const Result& r : results)
+            if (r.key.kind == sar::TK_TURN && r.key.n == cols) return SAR_OK;
+        std::vector<Candidate> cs{{0, 0.f}, {1, 0.f}, {2, 0.f}};
+        sar_status r = time_candidates(
+            cs, [&](int v) { return sar::launch_corner_turn(in, out, rows, cols, v, s); }, s);
+        if (r == SAR_OK) results.push_back(pick(Key{sar::TK_TURN, cols, SAR_FP32}, cs));
+        return r;
+    };
+    if (p->precision != SAR_FP32_HALF_STORAGE) {
+        if (p->schedule != SAR_TURN_FREE) st = tune_turn(Na, Nr);
+        if (st == SAR_OK && p->transpose_back) st = tune_turn(Nr, Na);
+        if (st != SAR_OK) return done(st);
+    }
+    // the turn-free azimuth strips
+    if (p->schedule == SAR_TURN_FREE && fp32 && Na <= 4096) {
+        std::vector<Candidate> cs{{0, 0.f}, {1, 0.f}};
+        st = time_candidates(
+            cs,
+            [&](int v) {
+                return sar::launch_line_strip(!hyper, Na, in, out, Nr, Nr, hyper ? nullptr : tb.Ha,
+                                              tb.tw_a, 1.f, v, s);
+            },
+            s);
+        if (st != SAR_OK) return done(st);
+        results.push_back(pick(Key{sar::TK_STRIP, Na, SAR_FP32}, cs));
+    }
     // the batched fused line kernel (LFM fused scenes are batched)
     if (!hyper && fused) {
         if ((st = tune_batch(Nr, Na, tb.Hr, tb.tw_r)) == SAR_OK) st = tune_batch(Na, Nr, tb.Ha, tb.tw_a);

@@ -16,7 +16,7 @@ from sarsim import batch_configs, config, simulate
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["fused", "fwd", "inv", "rcmc", "batch_fused"]
+KINDS = ["fused", "fwd", "inv", "rcmc", "batch_fused", "turn", "strip"]
 
 
 def arch():
@@ -71,9 +71,9 @@ def test_autotune_writes_cache_and_plans_use_it(tmp_path, name):
     kinds = {(e["kind"], e["n"]) for e in lines}
     if cfg["az_model"] == "lfm":
         want = {("fused", cfg["Nr"]), ("fused", cfg["Na"]), ("batch_fused", cfg["Nr"]),
-                ("batch_fused", cfg["Na"])}
+                ("batch_fused", cfg["Na"]), ("turn", cfg["Nr"])}
     else:
-        want = {("fused", cfg["Nr"]), ("fwd", cfg["Na"]), ("rcmc", cfg["Na"])}
+        want = {("fused", cfg["Nr"]), ("fwd", cfg["Na"]), ("rcmc", cfg["Na"]), ("turn", cfg["Nr"])}
     assert kinds == want
     for e in lines:
         assert e["arch"] == arch()
@@ -200,3 +200,53 @@ def test_split_layout_line_fft_bit_identical(tmp_path, n, inverse):
     assert np.array_equal(outs[3].view(np.uint32), outs[1].view(np.uint32))
     ref = np.stack([O.fft(r, inverse=bool(inverse)) for r in x])
     assert rel_l2(outs[2], ref) < 2e-6
+
+
+@pytest.mark.parametrize("rows, cols", [(4096, 4096), (256, 4096), (2048, 512), (64, 128)])
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_corner_turn_grids_bit_exact(tmp_path, rows, cols, variant):
+    """Every corner-turn grid the tuner can choose (five or four workgroups
+    per CU, or one per tile) moves every sample to its transposed place."""
+    torch = torch_cuda()
+    write_cache(tmp_path / "t.jsonl", [("turn", cols, 0, variant)])
+    cfg = config("c1", Nr=cols, Na=rows, range_len=min(64, cols // 2), range_tbp=16.0,
+                 az_len=min(64, rows // 2), az_tbp=16.0)
+    rng = np.random.Generator(np.random.PCG64(900 + rows + cols + variant))
+    x = (rng.standard_normal((rows, cols)) + 1j * rng.standard_normal((rows, cols))).astype(np.complex64)
+    out = torch.empty((cols, rows), dtype=torch.complex64, device="cuda")
+    with sar.Plan(cfg) as p:
+        sar.sar_corner_turn(p.handle, dev(x), out, rows, cols)
+        got = host(out)
+    assert np.array_equal(got.view(np.uint32), np.ascontiguousarray(x.T).view(np.uint32))
+
+
+@pytest.mark.parametrize("name, na", [("c1", 4096), ("c2", 4096), ("c1", 1024), ("c1", 256)])
+def test_strip_widths_bit_identical(tmp_path, name, na):
+    """Half-width turn-free strips give the default width's image bit for
+    bit (LFM and hyperbolic; 4096-point lines in strips of two, 1024- and
+    256-point lines in strips of eight)."""
+    if name == "c1":
+        cfg = config("c1", Nr=512, Na=na, range_len=64, range_tbp=32.0, az_len=min(64, na // 2),
+                     az_tbp=min(32.0, na / 4), n_targets=1, spacing=4)
+        sc = simulate(cfg)
+    else:
+        cfg, sc, _ = scene("c2")
+    base = np.ascontiguousarray(run(cfg, sc.raw, schedule="turn_free"))
+    write_cache(tmp_path / "t.jsonl", [("strip", cfg["Na"], 0, 1)])
+    assert sar.sar_tune_variant(_lib.TUNE_STRIP, cfg["Na"], 0) == 1
+    half = np.ascontiguousarray(run(cfg, sc.raw, schedule="turn_free"))
+    assert np.array_equal(half.view(np.uint32), base.view(np.uint32))
+
+
+def test_autotune_turn_free_tunes_strips(tmp_path):
+    """A turn-free plan has no corner turn: the tuner times its strip widths
+    instead, and the plan built afterwards uses the winner."""
+    cfg, sc, ref = scene("c2")
+    path = tmp_path / "tune.jsonl"
+    sar.sar_autotune(sar.make_params(cfg, schedule="turn_free"), str(path))
+    lines = [json.loads(l) for l in path.read_text().splitlines()]
+    kinds = {(e["kind"], e["n"]) for e in lines}
+    assert ("strip", cfg["Na"]) in kinds and not any(k == "turn" for k, _ in kinds), kinds
+    sar.sar_tune_load(str(path))
+    img = run(cfg, sc.raw, schedule="turn_free")
+    assert rel_l2(img, ref) <= 1e-5

@@ -25,6 +25,11 @@ CACHE = """\
 {"arch":"gfx950","kind":"fused","n":1024,"prec":2,"variant":1}
 not json at all
 {"arch":"gfx950","kind":"fwd","n":256,"prec":0}
+{"arch":"gfx950","kind":"turn","n":4096,"prec":0,"variant":2}
+{"arch":"gfx950","kind":"turn","n":2048,"prec":0,"variant":3}
+{"arch":"gfx950","kind":"turn","n":1024,"prec":1,"variant":1}
+{"arch":"gfx950","kind":"strip","n":4096,"prec":0,"variant":1}
+{"arch":"gfx950","kind":"strip","n":2048,"prec":0,"variant":2}
 """
 
 
@@ -64,6 +69,12 @@ def test_invalid_lines_are_ignored(cache):
     assert v(_lib.TUNE_RCMC, 1024, 2) == 0           # the wide RCMC kernel is FP32 only
     assert v(_lib.TUNE_BATCH_FUSED, 1024, 1) == 0    # no persistent split grids
     assert v(_lib.TUNE_FUSED, 1024, 2) == 0          # table twiddles are FP32 only
+    # corner-turn grids (0..2) and strip widths (0, 1), keyed as FP32
+    assert v(_lib.TUNE_TURN, 4096, 0) == 2
+    assert v(_lib.TUNE_TURN, 2048, 0) == 0           # no fourth grid
+    assert v(_lib.TUNE_TURN, 1024, 1) == 0           # not keyed by a split precision
+    assert v(_lib.TUNE_STRIP, 4096, 0) == 1
+    assert v(_lib.TUNE_STRIP, 2048, 0) == 0          # half width is the only other width
 
 
 def test_other_arch_and_clear(cache):
