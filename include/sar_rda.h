@@ -298,7 +298,9 @@ void sar_batch_destroy(sar_batch_t batch);
  *          of two table loads per radix-16 pass; FP32 butterflies only);
  *          kinds 1 and 2 (FP32): bit 1 = real and imaginary parts exchanged
  *          through LDS as two float arrays (the split layout of the MFMA
- *          passes; else one array of complex pairs);
+ *          passes; else one array of complex pairs); bit 2 (FP32, N <= 8192)
+ *          = twice the default lines per workgroup (8192 points per
+ *          workgroup up to N = 4096, two lines at 8192);
  *   kind 3 RCMC + azimuth kernel: bit 0 as above for its IFFT, bit 1 = one
  *          output row per line slot (else two rows sharing their gathers),
  *          bit 2 = the two rows on two line slots' threads instead of one's

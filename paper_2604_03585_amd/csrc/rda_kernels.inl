@@ -119,9 +119,11 @@ __device__ __forceinline__ float2 h2_to_f2(h2_t v, float scale)
 {
     return make_float2((float)v.x * scale, (float)v.y * scale);
 }
-template <int N> struct LineLaunch {
+// X: a multiple of the default lines per workgroup (the autotuner's 2x
+// candidate of the FP32 line kernels).
+template <int N, int X = 1> struct LineLaunch {
     static constexpr int T = LineGeom<N>::T;
-    static constexpr int LPW = T >= 256 ? 1 : 256 / T;     // lines per workgroup
+    static constexpr int LPW = (T >= 256 ? 1 : 256 / T) * X;   // lines per workgroup
     static constexpr int BLOCK = LPW * T;
     // Register policy of the fused FFT*H*IFFT kernels (measured on gfx950):
     // the inverse transform reuses the forward pass's twiddle products when
@@ -234,13 +236,13 @@ __device__ __forceinline__ void line_transform(float2 (&x)[line_e(N)], float2* _
     }
 }
 
-template <int N, int KIND, int PREC, bool TWP, bool SPLIT = false>
+template <int N, int KIND, int PREC, bool TWP, bool SPLIT = false, int X = 1>
 __device__ __forceinline__ void line_group(const float2* in, float2* out, int lines,
                                            const float2* __restrict__ H,
                                            const float2* __restrict__ tw, float scale, int g,
                                            float2* smem)
 {
-    using L = LineLaunch<N>;
+    using L = LineLaunch<N, X>;
     constexpr int E = line_e(N);
     const int sub = threadIdx.x / L::T, t = threadIdx.x % L::T;
     const int line = g * L::LPW + sub;
@@ -308,15 +310,16 @@ k_line_strip(const float2* __restrict__ in, float2* __restrict__ out, int cols, 
     store_line<N>(x, out + (size_t)(n0 + sub) * N, t);
 }
 
-template <int N, int KIND, int PREC, bool TWP, bool SPLIT = false>
-__global__ __launch_bounds__(LineLaunch<N>::BLOCK)
+template <int N, int KIND, int PREC, bool TWP, bool SPLIT = false, int X = 1>
+__global__ __launch_bounds__((LineLaunch<N, X>::BLOCK))
 __attribute__((amdgpu_waves_per_eu(line_wpe<N, PREC>()))) void
 k_line(const float2* in, float2* out, int lines, const float2* __restrict__ H,
        const float2* __restrict__ tw, float scale)
 {
     static_assert(!SPLIT || (PREC == PREC_FP32 && KIND != LK_FUSED), "split layout: FP32 FFT only");
+    static_assert(X == 1 || PREC == PREC_FP32, "more lines per workgroup: FP32 butterflies only");
     extern __shared__ __align__(16) float2 smem[];
-    line_group<N, KIND, PREC, TWP, SPLIT>(in, out, lines, H, tw, scale, blockIdx.x, smem);
+    line_group<N, KIND, PREC, TWP, SPLIT, X>(in, out, lines, H, tw, scale, blockIdx.x, smem);
 }
 
 // Batched form: the line groups of many scenes (tasks) in one launch.  The
@@ -1344,6 +1347,25 @@ static hipError_t set_lds_limit()
     return hipSuccess;
 }
 
+// FP32 line kernel with X times the default lines per workgroup.
+template <int N, int KIND, bool TWP, bool SPLIT, int X>
+static hipError_t launch_k_line_x(const float2* in, float2* out, int lines, const float2* H,
+                                  const float2* tw, float scale, hipStream_t s)
+{
+    using L = LineLaunch<N, X>;
+    static const hipError_t attr =
+        L::LDS_BYTES <= 64 * 1024
+            ? hipSuccess
+            : hipFuncSetAttribute((const void*)k_line<N, KIND, PREC_FP32, TWP, SPLIT, X>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, L::LDS_BYTES);
+    if (attr != hipSuccess) return attr;
+    const int groups = (lines + L::LPW - 1) / L::LPW;
+    if (groups == 0) return hipSuccess;
+    SAR_LAUNCH((k_line<N, KIND, PREC_FP32, TWP, SPLIT, X>), dim3(groups), dim3(L::BLOCK),
+               L::LDS_BYTES, s, in, out, lines, H, tw, scale);
+    return hipGetLastError();
+}
+
 template <int N, int KIND, int PREC>
 static hipError_t launch_k_line(const float2* in, float2* out, int lines, const float2* H,
                                 const float2* tw, float scale, int variant, hipStream_t s)
@@ -1352,7 +1374,20 @@ static hipError_t launch_k_line(const float2* in, float2* out, int lines, const 
     const int groups = (lines + L::LPW - 1) / L::LPW;
     if (groups == 0) return hipSuccess;
     // variant bit 0: twiddles from the table (FP32 butterflies only); bit 1
-    // (FP32 forward / inverse): the split real/imaginary exchange layout
+    // (FP32 forward / inverse): the split real/imaginary exchange layout;
+    // bit 2 (FP32, N <= 8192): twice the lines per workgroup
+    if constexpr (PREC == PREC_FP32 && N <= 8192) {
+        if (variant & 4) {
+            const bool tab = variant & 1;
+            if constexpr (KIND != LK_FUSED) {
+                if (variant & 2)
+                    return tab ? launch_k_line_x<N, KIND, false, true, 2>(in, out, lines, H, tw, scale, s)
+                               : launch_k_line_x<N, KIND, true, true, 2>(in, out, lines, H, tw, scale, s);
+            }
+            return tab ? launch_k_line_x<N, KIND, false, false, 2>(in, out, lines, H, tw, scale, s)
+                       : launch_k_line_x<N, KIND, true, false, 2>(in, out, lines, H, tw, scale, s);
+        }
+    }
     if constexpr (PREC == PREC_FP32 && KIND != LK_FUSED) {
         if (variant & 2) {
             if (variant & 1)

@@ -63,9 +63,9 @@ bool valid_variant(int kind, int prec, int v)
     if (kind == sar::TK_STRIP) return prec == SAR_FP32 && (v == 0 || v == 1);
     if (prec != SAR_FP32) return v == 0 || (kind == sar::TK_RCMC && v == 2);
     switch (kind) {
-    case sar::TK_FUSED: return v == 0 || v == 1;
+    case sar::TK_FUSED: return v == 0 || v == 1 || v == 4 || v == 5;
     case sar::TK_FWD:
-    case sar::TK_INV: return v >= 0 && v <= 3;
+    case sar::TK_INV: return v >= 0 && v <= 7;
     case sar::TK_RCMC: return v >= 0 && v <= 7;
     case sar::TK_BATCH_FUSED: return v >= 0 && v <= 15 && (v & 2) == 0;
     default: return false;
@@ -375,6 +375,10 @@ sar_status sar_autotune(const sar_params* p, const char* cache_path)
         if (fp32 && kind != sar::TK_FUSED) {          // split real/imaginary exchange layout
             cs.push_back({2, 0.f});
             cs.push_back({3, 0.f});
+        }
+        if (fp32 && n <= 8192) {                      // twice the lines per workgroup
+            const size_t base = cs.size();
+            for (size_t i = 0; i < base; ++i) cs.push_back({cs[i].variant | 4, 0.f});
         }
         const sar::LineOp op = kind == sar::TK_FUSED ? sar::LineOp::Fused
                                : kind == sar::TK_FWD ? sar::LineOp::Forward

@@ -250,3 +250,32 @@ def test_autotune_turn_free_tunes_strips(tmp_path):
     sar.sar_tune_load(str(path))
     img = run(cfg, sc.raw, schedule="turn_free")
     assert rel_l2(img, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("n", [256, 1024, 4096, 8192])
+@pytest.mark.parametrize("kind", ["fused", "fwd", "inv"])
+@pytest.mark.parametrize("tab", [0, 1])
+def test_double_lines_per_workgroup_bit_identical(tmp_path, n, kind, tab):
+    """Twice the default lines per workgroup (variant bit 2) runs the same
+    per-line transforms: bit-identical to the default grouping.  The forward
+    and inverse cases use a line count that leaves the last workgroup partly
+    empty; the fused one runs over the plan's 64 lines."""
+    torch = torch_cuda()
+    lines = 64 if kind == "fused" else 3 * 2 * max(1, 256 // (n // 16)) + 1
+    cfg = config("c1", Nr=n, Na=64, range_len=max(2, n // 8), range_tbp=max(1.0, n / 16),
+                 az_len=16, az_tbp=8.0)
+    rng = np.random.Generator(np.random.PCG64(1000 + n + tab))
+    x = dev((rng.standard_normal((lines, n)) + 1j * rng.standard_normal((lines, n)))
+            .astype(np.complex64))
+    outs = []
+    for v in (tab, tab | 4):
+        write_cache(tmp_path / f"t{v}.jsonl", [(kind, n, 0, v)])
+        assert sar.sar_tune_variant(KINDS.index(kind), n, 0) == v
+        out = torch.empty((lines, n), dtype=torch.complex64, device="cuda")
+        with sar.Plan(cfg) as p:
+            if kind == "fused":
+                sar.sar_range_compress(p.handle, x, out)
+            else:
+                sar.sar_fft_lines(p.handle, 0, int(kind == "inv"), x, out, lines)
+            outs.append(host(out))
+    assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32))

@@ -63,7 +63,7 @@ def test_invalid_lines_are_ignored(cache):
     assert v(_lib.TUNE_FUSED, 256, 7) == 0           # unknown precision
     assert v(_lib.TUNE_FWD, 256, 0) == 0             # no variant field
     assert v(_lib.TUNE_INV, 1024, 0) == 3            # split layout + table twiddles
-    assert v(_lib.TUNE_FWD, 1024, 0) == 0            # bit 2 is not a line-kernel variant
+    assert v(_lib.TUNE_FWD, 1024, 0) == 4            # twice the lines per workgroup
     # split precisions: default kernels and the one-row RCMC kernel only
     assert v(_lib.TUNE_RCMC, 2048, 1) == 2
     assert v(_lib.TUNE_RCMC, 1024, 2) == 0           # the wide RCMC kernel is FP32 only
