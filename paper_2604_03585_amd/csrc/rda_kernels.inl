@@ -263,7 +263,7 @@ __device__ __forceinline__ void line_group(const float2* in, float2* out, int li
 // read straight from the range pass's [Na][Nr] output, so no corner turn is
 // needed.  Each row of the strip is C consecutive samples (C * 8 bytes: 32 B
 // at 4096 points, 64 B at 2048, 128 B at 1024 and below); the workgroup
-// reads the C x N strip with consecutive lanes on consecutive samples,
+// reads the C x N strip with consecutive lanes on consecutive sample pairs,
 // regroups it through LDS into one line per slot of T = N/16 threads, runs
 // the same line transform as k_line (so the results are bit-identical to
 // the turned path) and stores each line contiguously: out is [Nr][Na].
@@ -293,11 +293,16 @@ k_line_strip(const float2* __restrict__ in, float2* __restrict__ out, int cols, 
     const int g = xcd_group(blockIdx.x, cols / C);
     const int n0 = g * C;
     const int u = threadIdx.x;
+    // 16-byte loads: lanes take pairs of adjacent columns, C / 2 lanes per
+    // row (fewer, wider requests for the same short runs)
+    static_assert(C % 2 == 0, "pairs of columns");
 #pragma unroll
-    for (int p = 0; p < E; ++p) {
-        const int e = u + p * S::BLOCK;           // sample (row m, column c) of the strip
-        const int m = e / C, c = e % C;
-        smem[c * S::STRIDE + lds_pad(m)] = in[(size_t)m * pitch + n0 + c];
+    for (int p = 0; p < E / 2; ++p) {
+        const int e = u + p * S::BLOCK;           // pair (row m, columns 2q, 2q+1) of the strip
+        const int m = e / (C / 2), q = e % (C / 2);
+        const float4 v = *(const float4*)(in + (size_t)m * pitch + n0 + 2 * q);
+        smem[(2 * q) * S::STRIDE + lds_pad(m)] = make_float2(v.x, v.y);
+        smem[(2 * q + 1) * S::STRIDE + lds_pad(m)] = make_float2(v.z, v.w);
     }
     __syncthreads();
     const int sub = u / T, t = u % T;
@@ -1593,7 +1598,8 @@ static hipError_t launch_strip_k(const float2* in, float2* out, int cols, int pi
             : hipFuncSetAttribute((const void*)k_line_strip<N, KIND, true, CW>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, S::LDS_BYTES);
     if (attr != hipSuccess) return attr;
-    if (cols % S::C != 0) return hipErrorInvalidValue;
+    // whole strips; 16-byte pair loads need an even pitch and an aligned base
+    if (cols % S::C != 0 || (pitch & 1) || ((uintptr_t)in & 15u)) return hipErrorInvalidValue;
     if (cols == 0) return hipSuccess;
     SAR_LAUNCH((k_line_strip<N, KIND, true, CW>), dim3(cols / S::C), dim3(S::BLOCK), S::LDS_BYTES,
                s, in, out, cols, pitch, H, tw, scale);
