@@ -33,6 +33,8 @@ def _both(torch, plan, raw):
 
 CASES = [  # (config, overrides, precision, schedule): largest first, then smaller
     ("c2", {}, "fp32", "fused"),
+    ("c2", {}, "fp32", "turn_free"),
+    ("c1", dict(Na=1024, Nr=512), "fp32", "turn_free"),
     ("c1", {}, "fp32", "fused"),
     ("c2", dict(Na=2048, Nr=1024, range_len=256, range_tbp=100.0), "fp32_halfstore", "fused"),
     ("c2", dict(Na=1024, Nr=1024, range_len=256, range_tbp=100.0), "fp32", "unfused"),
